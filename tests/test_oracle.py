@@ -1,0 +1,432 @@
+"""Pins of the CPU oracle against facts fixed outside it: hand-derived factors,
+exactly representable constructions, closed forms of the exponential kernel,
+LAPACK, numpy's IEEE casts, format bit definitions and published known-answer
+vectors.  CPU only."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _workload(L, rho, nugget):
+    sigma, x = synth.workload(L)
+    return sigma, x
+
+
+# ------------------------------------------------------------------ O1 factor
+def test_golden_3x3(orc):
+    rows = [l.split() for l in open(os.path.join(GOLD, "chol3x3.txt")) if l.strip() and not l.startswith("#")]
+    A = np.zeros((3, 3))
+    Lref = np.zeros((3, 3))
+    for i, j, a, l in rows:
+        i, j = int(i), int(j)
+        A[i, j] = A[j, i] = float(a)
+        Lref[i, j] = float(l)
+    L, info = orc.potrf(A)
+    assert info == 0
+    assert np.array_equal(L, Lref)
+
+
+def test_2x2_closed_form(orc):
+    a, b, c = 2.5, -0.75, 3.0
+    L, info = orc.potrf(np.array([[a, b], [b, c]]))
+    assert info == 0
+    ref = np.array([[np.sqrt(a), 0], [b / np.sqrt(a), np.sqrt(c - b * b / a)]])
+    assert np.allclose(L, ref, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n,seed", [(7, 1), (64, 2), (300, 3)])
+def test_integer_L0_exact(orc, n, seed):
+    L0 = synth.int_lower(n, seed)
+    A = L0 @ L0.T  # small integers: exact in FP64
+    L, info = orc.potrf(A)
+    assert info == 0
+    assert np.array_equal(L, L0)
+
+
+def test_lapack_crosscheck(orc):
+    sigma, x = synth.workload(20)
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    L, info = orc.potrf(A)
+    assert info == 0
+    Lnp = np.linalg.cholesky(A)
+    assert np.linalg.norm(L - Lnp) / np.linalg.norm(Lnp) < 1e-12
+
+
+def test_invariants(orc):
+    sigma, x = synth.workload(12)
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    L, info = orc.potrf(A)
+    assert info == 0
+    assert np.all(np.triu(L, 1) == 0)
+    assert np.all(np.diag(L) > 0)
+    L4, _ = orc.potrf(4.0 * A)  # scaling by a power of two: exact
+    assert np.array_equal(L4, 2.0 * L)
+    I, _ = orc.potrf(np.eye(9))
+    assert np.array_equal(I, np.eye(9))
+    d = np.array([4.0, 9.0, 0.25, 16.0])
+    D, _ = orc.potrf(np.diag(d))
+    assert np.array_equal(D, np.diag(np.sqrt(d)))
+
+
+def test_not_spd_info(orc):
+    A = np.diag([1.0, 2.0, -1.0, 3.0])
+    _, info = orc.potrf(A)
+    assert info == 3
+    B = np.array([[1.0, 2.0], [2.0, 1.0]])
+    _, info = orc.potrf(B)
+    assert info == 2
+    Cn = np.diag([1.0, np.nan, 1.0])
+    _, info = orc.potrf(Cn)
+    assert info == 2
+
+
+def test_markov_closed_form_factor(orc):
+    """chol(D K D) from the closed form matches the right-looking definition."""
+    sigma, x = synth.workload(16)  # N = 256
+    A = orc.cov_dense(sigma, x, 5.0, 0.0)
+    L, info = orc.potrf(A)
+    assert info == 0
+    Lc = orc.markov_factor(sigma, x, 5.0)
+    assert np.max(np.abs(L - Lc)) / np.max(np.abs(Lc)) < 1e-11
+
+
+@pytest.mark.parametrize("rho,nugget", [(5.0, 0.0), (5.0, 1e-8), (2.0, 1e-8), (20.0, 1e-8)])
+def test_markov_logdet(orc, rho, nugget):
+    sigma, x = synth.workload(16)
+    A = orc.cov_dense(sigma, x, rho, nugget)
+    L, info = orc.potrf(A)
+    assert info == 0
+    ld_ref = orc.markov_logdet(sigma, x, rho, nugget)
+    assert abs(orc.logdet(L) - ld_ref) / abs(ld_ref) < 1e-11
+    sgn, ld_np = np.linalg.slogdet(A)
+    assert sgn > 0 and abs(ld_np - ld_ref) / abs(ld_ref) < 1e-11
+
+
+@pytest.mark.parametrize("nugget", [0.0, 1e-8])
+def test_markov_solve(orc, nugget):
+    sigma, x = synth.workload(16)
+    A = orc.cov_dense(sigma, x, 5.0, nugget)
+    B = synth.rhs(A.shape[0], 3)
+    Xc = orc.markov_solve(sigma, x, 5.0, nugget, B)
+    Xn = np.linalg.solve(A, B)
+    assert np.linalg.norm(Xc - Xn) / np.linalg.norm(Xn) < 1e-9
+    L, _ = orc.potrf(A)
+    Xo = orc.potrs(L, B)
+    assert np.linalg.norm(Xo - Xc) / np.linalg.norm(Xc) < 1e-9
+    # normwise backward error of the oracle solve
+    r = np.linalg.norm(B - A @ Xo) / (np.linalg.norm(A) * np.linalg.norm(Xo) + np.linalg.norm(B))
+    assert r < 1e-15
+
+
+def test_markov_logdet_matches_definition_larger(orc):
+    sigma, x = synth.workload(32)  # N = 1024, the small workload
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    L, info = orc.potrf(A)
+    assert info == 0
+    ld = orc.logdet(L)
+    ref = orc.markov_logdet(sigma, x, 5.0, 1e-8)
+    assert abs(ld - ref) / abs(ref) < 1e-10
+
+
+def test_residual_pins(orc):
+    L0 = synth.int_lower(40, 5)
+    A = L0 @ L0.T
+    assert orc.backward_error(A, L0) == 0.0
+    sigma, x = synth.workload(8)
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    L, _ = orc.potrf(A)
+    E0 = synth.normal(11, A.size).reshape(A.shape)
+    E0 = E0 + E0.T
+    tau = 1e-6
+    be = orc.backward_error(A + tau * E0, L)
+    want = tau * np.linalg.norm(E0) / np.linalg.norm(A + tau * E0)
+    assert abs(be - want) / want < 1e-3
+    # tile residuals add up to the full residual (strict-lower tiles twice)
+    t2 = orc.tile_residual2(A + tau * E0, L, 16)
+    tot = sum(t2[i, j] * (1 if i == j else 2) for i in range(t2.shape[0]) for j in range(i + 1))
+    full = be * np.linalg.norm(A + tau * E0)
+    assert abs(np.sqrt(tot) - full) / full < 1e-10
+
+
+def test_lower_matmul(orc):
+    L0 = np.tril(synth.normal(3, 50 * 50).reshape(50, 50))
+    Z = synth.normal(4, 50 * 7).reshape(50, 7)
+    assert np.allclose(orc.lower_matmul(L0, Z), L0 @ Z, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------------ formats
+def _rand_doubles(seed, n):
+    u = synth.uniform01(seed, n)
+    e = np.floor(synth.uniform01(seed + 1, n) * 80 - 50)
+    s = np.where(synth.uniform01(seed + 2, n) < 0.5, -1.0, 1.0)
+    return s * (0.5 + u) * 2.0 ** e
+
+
+def test_round_f32_matches_numpy(orc):
+    v = np.concatenate([_rand_doubles(1, 2000), [0.0, 1e-45, 3e-39, -7e-46, 3.5e38, 1e39]])
+    got = orc.round_to(v, orc.F32)
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float32).astype(np.float64)
+    assert np.array_equal(got, ref)
+
+
+def test_round_f16_matches_numpy(orc):
+    v = np.concatenate([_rand_doubles(5, 3000) * 1e-3, [65504.0, 65519.0, 65520.0, 6e-8, 2.98e-8, 2.99e-8, 1e-9]])
+    got = orc.round_to(v, orc.F16)
+    with np.errstate(over="ignore"):
+        ref = v.astype(np.float16).astype(np.float64)
+    assert np.array_equal(got, ref)
+
+
+def test_e4m3_table_and_rounding(orc):
+    codes = [c for c in range(256) if not np.isnan(orc.e4m3_decode(c))]
+    vals = np.array(sorted({orc.e4m3_decode(c) for c in codes}))
+    assert vals.max() == 448.0 and vals.min() == -448.0
+    assert np.min(vals[vals > 0]) == 2.0 ** -9
+    assert np.isnan(orc.e4m3_decode(0x7F)) and np.isnan(orc.e4m3_decode(0xFF))
+    assert len(codes) == 254
+    pos = vals[vals >= 0]
+    # brute force nearest with ties to an even code (even mantissa)
+    def nearest(a):
+        d = np.abs(pos - a)
+        best = np.flatnonzero(d == d.min())
+        if len(best) == 1:
+            return pos[best[0]]
+        for bi in best:
+            m = [c for c in range(128) if orc.e4m3_decode(c) == pos[bi]][0] & 7
+            if m % 2 == 0:
+                return pos[bi]
+        raise AssertionError
+    v = np.abs(_rand_doubles(9, 600)) * 2.0 ** -20
+    v = np.concatenate([v, [448.0, 460.0, 480.0, 1e5, 2.0 ** -10, 3 * 2.0 ** -11, 2.0 ** -9 * 1.5, 17.0, 18.0, 19.0]])
+    got = orc.round_to(v, orc.E4M3)
+    for a, g in zip(v, got):
+        want = 448.0 if a >= 448.0 else nearest(a)
+        assert g == want, (a, g, want)
+    assert orc.round_to(np.array([-17.0]), orc.E4M3)[0] == -16.0  # tie to even
+
+
+def test_round_bf16_bruteforce(orc):
+    v = _rand_doubles(13, 500)
+    got = orc.round_to(v, orc.BF16)
+    for a, g in zip(v, got):
+        e = np.floor(np.log2(abs(a)))
+        ulp = 2.0 ** (e - 7)
+        lo = np.floor(abs(a) / ulp) * ulp
+        cands = [lo, lo + ulp]
+        d = [abs(abs(a) - c) for c in cands]
+        want = cands[int(np.argmin(d))]
+        assert abs(g) == want and np.sign(g) == np.sign(a)
+
+
+def test_scale_exp(orc):
+    for fmt, mx in [(orc.F16, 65504.0), (orc.E4M3, 448.0)]:
+        for a in np.abs(_rand_doubles(21, 300)) * 1e-20:
+            t = orc.scale_exp(a, fmt)
+            assert a * 2.0 ** t <= mx < a * 2.0 ** (t + 1)
+        assert orc.scale_exp(0.0, fmt) == 0
+    assert orc.scale_exp(1e-30, orc.BF16) == 0 and orc.scale_exp(1e-30, orc.F32) == 0
+
+
+def test_unit_roundoffs(orc):
+    assert orc.unit_roundoff(orc.F64) == 2.0 ** -53
+    assert orc.unit_roundoff(orc.F32) == 2.0 ** -24
+    assert orc.unit_roundoff(orc.BF16) == 2.0 ** -8
+    assert orc.unit_roundoff(orc.F16) == 2.0 ** -11
+    assert orc.unit_roundoff(orc.E4M3) == 2.0 ** -4
+
+
+# ------------------------------------------------------------------ maps
+def test_map_norm_rule(orc):
+    sigma, x = synth.workload(24)  # N = 576
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    b = 64
+    fro2, amax, tot = orc.tile_norms(A, b)
+    assert abs(tot - np.linalg.norm(A)) / tot < 1e-13
+    nt = fro2.shape[0]
+    m0 = orc.map_norm(fro2, tot, 1e-30)
+    assert np.all(m0 == 0)
+    mh = orc.map_norm(fro2, tot, 1e30)
+    for I in range(nt):
+        for J in range(I + 1):
+            assert mh[I, J] == (3 if I - J > 1 else 0)
+    m2 = orc.map_norm(fro2, tot, 1e30, band=3, allowed=0b0011)
+    for I in range(nt):
+        for J in range(I + 1):
+            assert m2[I, J] == (1 if I - J > 3 else 0)
+    # the rule: lowest allowed class whose unit roundoff times the tile norm fits the budget
+    eps = 1e-9
+    m = orc.map_norm(fro2, tot, eps, lo16=orc.F16)
+    us = [2.0 ** -53, 2.0 ** -24, 2.0 ** -11, 2.0 ** -4]
+    thr = eps * tot / nt
+    for I in range(nt):
+        for J in range(I - 1):
+            f = np.sqrt(fro2[I, J])
+            c = m[I, J]
+            assert f * us[c] <= thr or c == 0
+            if c < 3:
+                assert f * us[c + 1] > thr
+    # monotone in eps
+    m3 = orc.map_norm(fro2, tot, 1e-6, lo16=orc.F16)
+    assert np.all(m3 >= m)
+
+
+# ------------------------------------------------------------------ O2 mixed replay
+def _class_map(nt, seed):
+    u = synth.uniform01(seed, nt * nt).reshape(nt, nt)
+    m = np.floor(u * 4).astype(np.uint8)
+    m = np.tril(m, -1)
+    return np.asfortranarray(m)
+
+
+@pytest.mark.parametrize("lo16", [3, 2])
+def test_mp_integer_exact_any_map(orc, lo16):
+    """With A = L0 L0^T (small integers) every stage is exact in every class,
+    so the mixed replay must return L0 bit for bit whatever the map."""
+    n, b = 256, 32
+    L0 = synth.int_lower(n, 17)
+    A = L0 @ L0.T
+    nt = n // b
+    cmap = _class_map(nt, 23)
+    assert set(np.unique(cmap[np.tril_indices(nt, -1)])) == {0, 1, 2, 3}
+    Lh, info, ts = orc.mp_factor(A, b, cmap, lo16=lo16)
+    assert info == 0
+    assert np.array_equal(Lh, L0)
+
+
+def test_mp_all_fp64_matches_o1(orc):
+    sigma, x = synth.workload(16)
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    L, _ = orc.potrf(A)
+    nt = (A.shape[0] + 63) // 64
+    Lh, info, _ = orc.mp_factor(A, 64, np.zeros((nt, nt), np.uint8))
+    assert info == 0
+    assert np.linalg.norm(Lh - L) / np.linalg.norm(L) < 1e-13
+    assert orc.backward_error(A, Lh) < 1e-15
+
+
+def test_mp_padding(orc):
+    """N not a multiple of b: the identity padding leaves factor and logdet unchanged."""
+    sigma, x = synth.workload(15)  # N = 225, b = 64 -> 4 tiles, last has 33 rows
+    A = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    L, _ = orc.potrf(A)
+    Lh, info, _ = orc.mp_factor(A, 64, np.zeros((4, 4), np.uint8))
+    assert info == 0
+    assert np.linalg.norm(Lh - L) / np.linalg.norm(L) < 1e-13
+    assert abs(orc.logdet(Lh) - orc.markov_logdet(sigma, x, 5.0, 1e-8)) < 1e-9 * abs(orc.logdet(L))
+
+
+@pytest.mark.parametrize("cls,u", [(1, 2.0 ** -24), (2, 2.0 ** -11), (3, 2.0 ** -4)])
+def test_mp_error_scales_with_precision(orc, cls, u):
+    """All off-band tiles in one class: the backward error lands at that class's
+    rounding level relative to the off-band part of Sigma."""
+    sigma, x = synth.workload(16)
+    # a well-conditioned variant (larger diagonal perturbation), so that even
+    # all-FP8 off-band tiles keep the perturbed matrix positive definite
+    A = orc.cov_dense(sigma, x, 5.0, 1e-2)
+    b = 32
+    nt = A.shape[0] // b
+    cmap = np.zeros((nt, nt), np.uint8)
+    for I in range(nt):
+        for J in range(I - 1):
+            cmap[I, J] = cls
+    Lh, info, ts = orc.mp_factor(A, b, cmap, lo16=orc.F16)
+    assert info == 0
+    fro2, _, tot = orc.tile_norms(A, b)
+    off = np.sqrt(sum(2 * fro2[I, J] for I in range(nt) for J in range(I - 1)))
+    be = orc.backward_error(A, Lh) * tot
+    assert be <= 4 * u * off * np.sqrt(nt)
+    assert be >= 0.01 * u * off
+    # stored low-precision tiles are exactly representable in their format
+    if cls >= 2:
+        fmt = orc.F16 if cls == 2 else orc.E4M3
+        for I in range(2, nt):
+            tile = Lh[I * b:(I + 1) * b, 0:b] * 2.0 ** ts[I, 0]
+            assert np.array_equal(orc.round_to(tile[:4, :4], fmt), tile[:4, :4])
+
+
+def test_mp_not_spd(orc):
+    A = np.eye(64)
+    A[40, 40] = -1.0
+    Lh, info, _ = orc.mp_factor(A, 16, np.zeros((4, 4), np.uint8))
+    assert info == 41
+
+
+# ------------------------------------------------------------------ Philox draws
+def test_philox_kat(orc):
+    rows = [l.split() for l in open(os.path.join(GOLD, "philox_kat.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        assert orc.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_normal_draws_moments(orc):
+    z, raw = orc.normal_draws(2, 200001)
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 1) < 0.01
+    o = orc.philox4x32_10([1, 0, 0, 0], [2, 0])
+    assert list(raw[4:8]) == o
+
+
+# ------------------------------------------------------------------ selector MLP
+def _params(orc, seed, scale=0.3):
+    return np.ascontiguousarray(synth.normal(seed, orc.NPARAM) * scale)
+
+
+def test_mlp_forward_hand_case(orc):
+    P = np.zeros(orc.NPARAM)
+    # W1 = [I_8; 0], b1 = 0 -> h1 = relu(x) on the first 8 units
+    for i in range(8):
+        P[i * 8 + i] = 1.0
+    off_w2 = 512 + 64
+    for i in range(8):
+        P[off_w2 + i * 64 + i] = 2.0  # h2_i = relu(2 h1_i)
+    off_b2 = off_w2 + 4096
+    off_w3 = off_b2 + 64
+    for c in range(4):
+        P[off_w3 + c * 64 + c] = 1.0
+        P[off_w3 + c * 64 + 4 + c] = -1.0
+    P[off_w3 + 256 + 0] = 0.5  # b3
+    x = np.array([[1.0, -2.0, 3.0, 0.5, 0.25, 4.0, -1.0, 2.0]])
+    z = orc.mlp_forward(P, x)
+    r = np.maximum(x[0], 0)
+    want = [2 * r[c] - 2 * r[4 + c] for c in range(4)]
+    want[0] += 0.5
+    assert np.allclose(z[0], want, rtol=0, atol=1e-15)
+
+
+def test_mlp_grad_finite_difference(orc):
+    P = _params(orc, 3)
+    X, y = synth.features_toy(16, 5)
+    cw = np.array([1.0, 1.5, 2.0, 0.5])
+    loss, g = orc.mlp_loss_grad(P, X.astype(np.float64), y, cw, 0.7)
+    idx = np.concatenate([np.arange(0, orc.NPARAM, 97), [orc.NPARAM - 1, orc.NPARAM - 2, orc.NPARAM - 4]])
+    h = 1e-6
+    for i in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += h
+        Pm[i] -= h
+        fd = (orc.mlp_loss_grad(Pp, X.astype(np.float64), y, cw, 0.7)[0]
+              - orc.mlp_loss_grad(Pm, X.astype(np.float64), y, cw, 0.7)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+
+
+def test_mlp_training_decreases_loss(orc):
+    P = _params(orc, 3, 0.2)
+    X, y = synth.features_toy(256, 7)
+    X = X.astype(np.float64)
+    cw = np.ones(4)
+    m, v = np.zeros_like(P), np.zeros_like(P)
+    l0 = orc.mlp_loss_grad(P, X, y, cw, 0.0)[0]
+    for s in range(1, 201):
+        _, g = orc.mlp_loss_grad(P, X, y, cw, 0.0)
+        orc.adam_step(P, g, m, v, s, lr=3e-3)
+    l1 = orc.mlp_loss_grad(P, X, y, cw, 0.0)[0]
+    assert l1 < 0.3 * l0
+    acc = np.mean(np.argmax(orc.mlp_forward(P, X), axis=1) == y)
+    assert acc > 0.9
