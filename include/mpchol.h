@@ -1,0 +1,240 @@
+/*
+ * mpchol.h -- mixed-precision tile Cholesky of a dense SPD covariance on one
+ * AMD Instinct MI355X (gfx950), and the products built on the factor.
+ *
+ * The operation (paper Sec. III.A.3): factor the covariance of the
+ * spherical-harmonic coefficient vectors, U = V V^T with V lower triangular,
+ * and use V for the log-determinant, for solves, and for emulation draws
+ * xi = V z with z ~ N(0, I) (Sec. III.B).  The factorization is the tile
+ * algorithm whose tasks are POTRF, TRSM, SYRK and GEMM (Sec. II.C, Sec. V.A),
+ * with a precision chosen per tile (Sec. III.D; precision variants Sec. IV.B)
+ * and the conversion of each panel tile done once by its producer for all of
+ * its consumers (Sec. V.A).
+ *
+ * Conventions for every call:
+ *   - Return value: MPCHOL_OK (0), MPCHOL_NOT_SPD (1) or a negative error code.
+ *     No exception or C++ type crosses this interface.
+ *   - Matrices are column-major; "device" pointers are HIP device memory of
+ *     the handle's device, "host" pointers are ordinary host memory.
+ *   - Pointers need to stay valid only for the duration of the call; the
+ *     library copies what it keeps.  The handle owns all tile storage.
+ *   - All device work is ordered on the handle's stream.  Calls that return a
+ *     host scalar (logdet, backward_error, get_stats, factor's info)
+ *     synchronize that stream; the others only enqueue.
+ *   - A handle is single-threaded: calls on one handle must not overlap.
+ *   - Call order: create -> set_matrix | set_generator -> precision_map ->
+ *     factor -> {logdet, solve, sample, backward_error, get_factor}.  A call
+ *     made out of order returns MPCHOL_EORDER and changes nothing.
+ */
+#ifndef MPCHOL_H
+#define MPCHOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MPCHOL_OK 0
+#define MPCHOL_NOT_SPD 1       /* a diagonal pivot was not positive (or NaN) */
+#define MPCHOL_EINVAL (-1)     /* invalid argument */
+#define MPCHOL_ENOMEM (-2)     /* device allocation failed */
+#define MPCHOL_EHIP (-3)       /* a HIP runtime call failed */
+#define MPCHOL_EORDER (-4)     /* call out of order (see above) */
+#define MPCHOL_EBUDGET (-5)    /* backward-error budget missed after every fallback */
+#define MPCHOL_EUNSUPPORTED (-6)
+
+/* precision classes of a tile (the codes of a precision map) */
+#define MPCHOL_P64 0 /* FP64 storage and FP64 arithmetic */
+#define MPCHOL_P32 1 /* FP32 storage, FP32 products and accumulation */
+#define MPCHOL_P16 2 /* 16-bit storage (FP16 with a per-tile power-of-two scale, or BF16), FP32 accumulation */
+#define MPCHOL_P8 3  /* OCP FP8 E4M3FN with a per-tile power-of-two scale, FP32 accumulation */
+
+/* which 16-bit format the P16 class uses */
+#define MPCHOL_LO16_F16 0
+#define MPCHOL_LO16_BF16 1
+
+/* precision-map rules */
+#define MPCHOL_RULE_FP64 0    /* every tile FP64 (the plain FP64 path) */
+#define MPCHOL_RULE_NORM 1    /* tile-centric norm rule (Sec. III.D "numeric features of the tile") */
+#define MPCHOL_RULE_BAND 2    /* band rule (Sec. III.D band-based; variants DP/SP, DP/SP/HP, DP/HP of Sec. IV.B) */
+#define MPCHOL_RULE_USER 3    /* caller-supplied map */
+#define MPCHOL_RULE_LEARNED 4 /* learned selector (MLP inference kernel) with the norm rule as fallback */
+
+/* band variants for MPCHOL_RULE_BAND (Sec. IV.B) */
+#define MPCHOL_BAND_DP_SP 1    /* band in FP64, the rest FP32 */
+#define MPCHOL_BAND_DP_SP_HP 2 /* band in FP64, the next band holding >= 5% of the off-diagonal tiles FP32, rest 16-bit */
+#define MPCHOL_BAND_DP_HP 3    /* band in FP64, the rest 16-bit */
+
+typedef struct mpchol_handle *mpchol_t;
+
+typedef struct mpchol_opts {
+    int32_t device;      /* HIP device ordinal */
+    void *stream;        /* hipStream_t to order all work on; NULL = the null stream */
+    int32_t lo16;        /* MPCHOL_LO16_F16 or MPCHOL_LO16_BF16 */
+    int32_t band;        /* tiles with |I-J| <= band stay FP64 under NORM, BAND and LEARNED (default 1) */
+    uint32_t allowed;    /* bit mask of allowed classes (bit p for class p); FP64 is always allowed */
+    int32_t band_variant;/* MPCHOL_BAND_* used by MPCHOL_RULE_BAND */
+    int32_t verify;      /* LEARNED rule: check the backward error after factor and fall back on violation */
+    double verify_eps;   /* backward-error budget used by verify */
+    int32_t profile;     /* nonzero: time every update-GEMM launch with events (adds event overhead) */
+} mpchol_opts;
+
+typedef struct mpchol_stats {
+    int64_t n;
+    int32_t tile, nt;
+    int64_t tiles_per_class[4];  /* strict-lower tiles per class */
+    double flops_per_class[4];   /* task flops by class: POTRF b^3/3, TRSM b^3, SYRK b^3 in FP64, GEMM 2b^3 in its class */
+    double total_fro;            /* ||Sigma||_F of the valid part */
+    double t_map_ms;             /* last precision_map: norms, rule, load into work tiles */
+    double t_factor_ms;          /* last factor (all of its kernels, conversions included) */
+    double t_solve_ms, t_sample_ms, t_residual_ms;
+    double t_gemm_ms[4];         /* profile mode: summed update-GEMM kernel time per class in the last factor */
+    int64_t gemm_launches[4];    /* profile mode: number of those launches */
+    double gemm_flops[4];        /* flops of those launches */
+    int32_t fallbacks;           /* refactorizations made by verify */
+    int32_t rule_used;           /* rule of the map the last factor ran with */
+} mpchol_stats;
+
+/* Default options: device 0, null stream, FP16, band 1, all classes allowed. */
+void mpchol_default_opts(mpchol_opts *o);
+
+/* Create a handle for an n x n matrix in tiles of tile x tile (tile a multiple
+ * of 64, 64..2048).  n need not be a multiple of tile: the last tile row and
+ * column are padded with an identity block, which changes neither the factor
+ * nor the log-determinant.  Allocates the tile storage (about
+ * NT(NT+1)/2 * tile^2 * 8 bytes) and the panel buffers on o->device.
+ * o may be NULL (defaults).  On error *h is NULL. */
+int mpchol_create(mpchol_t *h, int64_t n, int32_t tile, const mpchol_opts *o);
+
+/* Free everything the handle owns.  Accepts NULL. */
+int mpchol_destroy(mpchol_t h);
+
+/* Use the caller's matrix A (lower part read, lda >= n).  on_device: A is
+ * device memory (else host).  The lower tiles are copied into a device
+ * FP64 copy kept for later loads and residuals. */
+int mpchol_set_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_device);
+
+/* Use the synthetic covariance generated on the device on demand,
+ *   Sigma_ij = sigma_i sigma_j exp(-|x_i - x_j| / rho) + nugget delta_ij,
+ * the exponential kernel over the ordered coefficient index with the
+ * diagonal perturbation that keeps it positive definite (Sec. III.A.3).
+ * sigma and x: host arrays of n doubles; rho > 0; nugget >= 0. */
+int mpchol_set_generator(mpchol_t h, const double *sigma, const double *x, double rho, double nugget);
+
+/* Choose the precision of every tile and load Sigma into the work tiles.
+ * Computes tile norms (FP64 on the device), applies `rule` with accuracy
+ * target eps (NORM: the lowest allowed class p with
+ * ||Sigma_IJ||_F u_p <= eps ||Sigma||_F / NT; tiles within the band and the
+ * diagonal stay FP64), then writes Sigma into FP64 work tiles (FP64 class)
+ * or FP32 work tiles (every lower class).
+ * user_map: host NT x NT uint8, column-major (entry I + J*NT), lower part
+ * read, required for RULE_USER, ignored otherwise (diagonal forced FP64).
+ * map_out: optional host NT x NT uint8 receiving the map (strict upper = 0).
+ * Synchronizes. */
+int mpchol_precision_map(mpchol_t h, int32_t rule, double eps, const uint8_t *user_map, uint8_t *map_out);
+
+/* Factor the loaded matrix in place (right-looking tile algorithm, Sec. V.A).
+ * *info = 0 on success, else the 1-based global column of the first failing
+ * pivot (returns MPCHOL_NOT_SPD).  Under RULE_LEARNED with opts.verify set,
+ * a backward error above opts.verify_eps (or a failing pivot) triggers a
+ * refactorization under RULE_NORM and then RULE_FP64 (counted in stats);
+ * MPCHOL_EBUDGET if all fail.  Synchronizes once at the end. */
+int mpchol_factor(mpchol_t h, int64_t *info);
+
+/* log det(Sigma) = 2 sum log diag(L), summed in FP64.  Synchronizes. */
+int mpchol_logdet(mpchol_t h, double *out);
+
+/* Overwrite device B (n x nrhs, ldb >= n, FP64) with Sigma^-1 B by forward
+ * and backward tile substitution; diagonal blocks in FP64, off-diagonal
+ * updates read each tile in its stored precision, exactly widened to FP64. */
+int mpchol_solve(mpchol_t h, int32_t nrhs, double *B, int64_t ldb);
+
+/* Emulation draws (Sec. III.B): device Y (n x ndraws, ldy >= n, FP32) =
+ * L Z with Z ~ N(0, I) generated on the device by Philox4x32-10 (key =
+ * seed) and Box-Muller in FP32; draw e (column-major index of Z) uses counter
+ * block e/4, entry e%4.  Tiles are read in their stored precision. */
+int mpchol_sample(mpchol_t h, int32_t ndraws, uint64_t seed, float *Y, int64_t ldy);
+
+/* As mpchol_sample with a caller-supplied device Z (n x ndraws, FP32). */
+int mpchol_sample_z(mpchol_t h, int32_t ndraws, const float *Z, int64_t ldz, float *Y, int64_t ldy);
+
+/* The draw sequence alone: device z (count FP32 normals) and optional device
+ * raw (count uint32 Philox outputs), same mapping as mpchol_sample. */
+int mpchol_normal_draws(mpchol_t h, int64_t count, uint64_t seed, float *z, uint32_t *raw);
+
+/* Relative backward error ||Sigma - L L^T||_F / ||Sigma||_F with the stored
+ * factor exactly widened to FP64 and FP64 accumulation.  Sigma comes from the
+ * generator or the kept copy of set_matrix.  tile_res2 (optional host NT x NT
+ * doubles, column-major) receives the squared residual norm of each lower
+ * tile (strict-lower entries of a diagonal tile counted twice).  Synchronizes. */
+int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2);
+
+/* Copy the factor's represented values into device L (n x n FP64, ldl >= n;
+ * the strict upper part is zeroed).  Valid after a successful factor. */
+int mpchol_get_factor(mpchol_t h, double *L, int64_t ldl);
+
+/* Host copy of the per-tile stored scale exponents (NT x NT int32,
+ * column-major): tile (I,J) represents values code * 2^-t. */
+int mpchol_get_tile_scales(mpchol_t h, int32_t *t);
+
+/* Fill *s (synchronizes). */
+int mpchol_get_stats(mpchol_t h, mpchol_stats *s);
+
+/* Static description of a status code. */
+const char *mpchol_strerror(int status);
+
+/* ---- learned precision selector -------------------------------------- */
+/* A multilayer perceptron 8 -> 64 -> 64 -> 4 (ReLU, FP32) mapping tile
+ * features to the classes {P64, P32, P16, P8}.  Parameter vector (FP32,
+ * MPCHOL_MLP_NPARAM values, row-major out x in): W1[64*8] b1[64] W2[64*64]
+ * b2[64] W3[4*64] b3[4].
+ * Features of tile (I,J) (FP32, computed on the device from FP64 norms):
+ *   f0 = log10(||S_IJ||_F NT / (eps ||S||_F))      f1 = log10(max|S_IJ| b NT / (eps ||S||_F))
+ *   f2 = (I-J)/NT   f3 = l(first row of I)/Lw   f4 = l(last row of I)/Lw   f5 = l(middle column of J)/Lw
+ *   f6 = log10(||S_II||_F/||S||_F)   f7 = log10(||S_JJ||_F/||S||_F)
+ * with l(i) = floor(sqrt(i)) the spherical-harmonic degree of index i,
+ * Lw = floor(sqrt(n-1)) + 1, and log10 of zero taken as -40. */
+#define MPCHOL_MLP_NPARAM 4996
+
+/* Set the selector weights used by RULE_LEARNED (host, nparam floats). */
+int mpchol_selector_set(mpchol_t h, const float *params, int64_t nparam);
+
+/* Host copy of the features of every strict-lower tile after a
+ * precision_map call: feats (NT*NT x 8, row-major by tile index I + J*NT;
+ * entries outside the strict lower part are zero).  eps as in the map. */
+int mpchol_selector_features(mpchol_t h, double eps, float *feats);
+
+/* Labels by greedy per-tile lowering under a measured backward-error budget:
+ * factor with every off-band tile at each class to measure per-tile
+ * residuals, lower tiles greedily by (estimated time saved)/(added squared
+ * residual) while the total stays within (eps ||S||_F)^2 / 2, then verify
+ * with one factorization and raise the worst tiles until it holds.
+ * labels: host NT x NT uint8 (the resulting map).  The handle must have a
+ * matrix set; its tiles are reloaded and refactored several times. */
+int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out);
+
+typedef struct mpchol_mlp *mpchol_mlp_t;
+
+/* Trainer object on the given device/stream (stream may be NULL). */
+int mpchol_mlp_create(mpchol_mlp_t *m, int32_t device, void *stream);
+int mpchol_mlp_destroy(mpchol_mlp_t m);
+/* host params in/out (nparam floats); set also zeroes the Adam moments */
+int mpchol_mlp_set_params(mpchol_mlp_t m, const float *params, int64_t nparam);
+int mpchol_mlp_get_params(mpchol_mlp_t m, float *params, int64_t nparam);
+/* loss and gradient (device grad, nparam floats) of the batch: device X
+ * (nb x 8 row-major), device y (nb int32 labels), host class weights cw[4];
+ * per-sample loss w_y (-log p_y) + alpha sum_{c>y} p_c, mean over the batch. */
+int mpchol_mlp_grad(mpchol_mlp_t m, const float *X, const int32_t *y, int64_t nb, const float *cw, float alpha,
+                    float *grad, float *loss);
+/* one Adam step (Kingma & Ba) on the batch; *loss (optional) = the batch loss before the step */
+int mpchol_mlp_train_step(mpchol_mlp_t m, const float *X, const int32_t *y, int64_t nb, const float *cw, float alpha,
+                          float lr, float *loss);
+/* logits (device nb x 4 row-major) and/or argmax classes (device nb int32) */
+int mpchol_mlp_predict(mpchol_mlp_t m, const float *X, int64_t nb, float *logits, int32_t *cls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,236 @@
+// MFMA block-GEMM cores for gfx950: acc(BM x BN) += A(BM x K) * B(BN x K)^T.
+//
+// Two operand layouts:
+//   * "cm" (FP64, FP32): A(r, k) = A[r + k*lda]  (a column-major tile: rows
+//     contiguous for each k), MFMA 16x16x4 (one element per lane);
+//   * "rm" (FP16, BF16, FP8): A(r, k) = A[r*lda + k]  (k contiguous), MFMA
+//     16x16x32 (eight elements per lane), FP32 accumulation.
+// 256 threads = 4 waves in a 2 x 2 grid; each wave owns (BM/2) x (BN/2) of the
+// block as (BM/32) x (BN/32) MFMA tiles of 16 x 16.  Operands are staged
+// through double-buffered LDS, the next K slice is fetched into registers
+// while the current one is multiplied.
+//
+// MFMA lane layout used (lane l = 0..63, g = l / 16, i = l % 16):
+//   16x16x4 :  a = A[i][g],          b = B[g][i]
+//   16x16x32:  a[j] = A[i][8g + j],  b[j] = B[8g + j][i]   (j = 0..7)
+//   result  :  d[v] = D[4g + v][i]   (v = 0..3) for the FP32-accumulating forms,
+//              d[v] = D[g + 4v][i]   for 16x16x4 FP64 (64-bit accumulator registers)
+#pragma once
+#include "common.h"
+
+namespace mpc {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Row (within a 16 x 16 MFMA tile) of accumulator element v of a lane in lane group g.
+template <typename T> __device__ inline int acc_row(int g, int v) { return sizeof(T) == 8 ? g + 4 * v : 4 * g + v; }
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------- cm (FP64 / FP32)
+template <typename T> struct CM;
+template <> struct CM<double> {
+    typedef double4_t acc_t;
+    static constexpr int PAD = 16;
+    __device__ static inline acc_t mfma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct CM<float> {
+    typedef float4_t acc_t;
+    static constexpr int PAD = 16;
+    __device__ static inline acc_t mfma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+template <typename T, int BM, int BN, int BK>
+struct CMShape {
+    static constexpr int VEC = 16 / sizeof(T);
+    static constexpr int LDM = BM + CM<T>::PAD, LDN = BN + CM<T>::PAD;
+    static constexpr int CA = BK * BM / VEC / 256;  // 16-byte chunks per thread for A
+    static constexpr int CB = BK * BN / VEC / 256;
+    static constexpr int MB = BM / 32, NB = BN / 32;
+    static constexpr size_t SMEM = sizeof(T) * (size_t)2 * BK * (LDM + LDN);
+    static_assert(CA >= 1 && CB >= 1, "block too small for 256 threads");
+    static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA K");
+};
+
+// acc -= A * B^T over K (K a multiple of BK).  `neg` selects the sign
+// convention: the caller passes acc to be updated as acc + sgn * A B^T.
+template <typename T, int BM, int BN, int BK>
+__device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb, int K,
+                                typename CM<T>::acc_t (&acc)[BM / 32][BN / 32], T *smem)
+{
+    typedef CMShape<T, BM, BN, BK> S;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int gi = lane & 15, gg = lane >> 4;
+    T *As = smem;                       // [2][BK][LDM]
+    T *Bs = smem + 2 * BK * S::LDM;     // [2][BK][LDN]
+    u32x4 ra[S::CA], rb[S::CB];
+    const int nk = K / BK;
+
+    auto gload = [&](int kt) {
+#pragma unroll
+        for (int c = 0; c < S::CA; ++c) {
+            int ch = tid + 256 * c;
+            int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
+            ra[c] = *(const u32x4 *)(A + r + (int64_t)(kt * BK + col) * lda);
+        }
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            int ch = tid + 256 * c;
+            int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
+            rb[c] = *(const u32x4 *)(B + r + (int64_t)(kt * BK + col) * ldb);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < S::CA; ++c) {
+            int ch = tid + 256 * c;
+            int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
+            *(u32x4 *)(As + (buf * BK + col) * S::LDM + r) = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            int ch = tid + 256 * c;
+            int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
+            *(u32x4 *)(Bs + (buf * BK + col) * S::LDN + r) = rb[c];
+        }
+    };
+
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload(kt + 1);
+        const T *as = As + cur * BK * S::LDM + wm * (BM / 2) + gi;
+        const T *bs = Bs + cur * BK * S::LDN + wn * (BN / 2) + gi;
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s) {
+            T fa[S::MB], fb[S::NB];
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m) fa[m] = as[(s * 4 + gg) * S::LDM + m * 16];
+#pragma unroll
+            for (int n = 0; n < S::NB; ++n) fb[n] = bs[(s * 4 + gg) * S::LDN + n * 16];
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                for (int n = 0; n < S::NB; ++n) acc[m][n] = CM<T>::mfma(fa[m], fb[n], acc[m][n]);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- rm (FP16 / BF16 / FP8)
+enum { RM_F16 = 0, RM_BF16 = 1, RM_FP8 = 2 };
+
+template <int KIND> struct RM;
+template <> struct RM<RM_F16> {
+    typedef uint16_t T;
+    typedef u32x4 frag_t;  // 8 halves
+    __device__ static inline float4_t mfma(frag_t a, frag_t b, float4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a), __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
+    }
+};
+template <> struct RM<RM_BF16> {
+    typedef uint16_t T;
+    typedef u32x4 frag_t;
+    __device__ static inline float4_t mfma(frag_t a, frag_t b, float4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
+    }
+};
+template <> struct RM<RM_FP8> {
+    typedef uint8_t T;
+    typedef u32x2 frag_t;  // 8 bytes
+    __device__ static inline float4_t mfma(frag_t a, frag_t b, float4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0, 0, 0);
+    }
+};
+
+template <int KIND, int BM, int BN, int BK>
+struct RMShape {
+    typedef typename RM<KIND>::T T;
+    static constexpr int ROWB = BK * (int)sizeof(T);       // bytes per staged row
+    static constexpr int LDB = ROWB + 16;                   // padded row stride in bytes
+    static constexpr int CPR = ROWB / 16;                   // 16-byte chunks per row
+    static constexpr int CA = BM * CPR / 256, CB = BN * CPR / 256;
+    static constexpr int MB = BM / 32, NB = BN / 32;
+    static constexpr size_t SMEM = (size_t)2 * (BM + BN) * LDB;
+    static_assert(CA >= 1 && CB >= 1, "block too small for 256 threads");
+    static_assert(BK % 32 == 0, "BK must be a multiple of the MFMA K");
+};
+
+template <int KIND, int BM, int BN, int BK>
+__device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int64_t lda,
+                                const typename RM<KIND>::T *__restrict__ B, int64_t ldb, int K,
+                                float4_t (&acc)[BM / 32][BN / 32], uint8_t *smem)
+{
+    typedef RMShape<KIND, BM, BN, BK> S;
+    typedef typename RM<KIND>::T T;
+    typedef typename RM<KIND>::frag_t F;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int gi = lane & 15, gg = lane >> 4;
+    uint8_t *As = smem;                         // [2][BM][LDB]
+    uint8_t *Bs = smem + 2 * BM * S::LDB;       // [2][BN][LDB]
+    u32x4 ra[S::CA], rb[S::CB];
+    const int nk = K / BK;
+
+    auto gload = [&](int kt) {
+#pragma unroll
+        for (int c = 0; c < S::CA; ++c) {
+            int ch = tid + 256 * c;
+            int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
+            ra[c] = *(const u32x4 *)((const uint8_t *)(A + (int64_t)row * lda + kt * BK) + cb);
+        }
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            int ch = tid + 256 * c;
+            int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
+            rb[c] = *(const u32x4 *)((const uint8_t *)(B + (int64_t)row * ldb + kt * BK) + cb);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < S::CA; ++c) {
+            int ch = tid + 256 * c;
+            int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
+            *(u32x4 *)(As + (buf * BM + row) * S::LDB + cb) = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            int ch = tid + 256 * c;
+            int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
+            *(u32x4 *)(Bs + (buf * BN + row) * S::LDB + cb) = rb[c];
+        }
+    };
+
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload(kt + 1);
+        const uint8_t *as = As + (cur * BM + wm * (BM / 2) + gi) * S::LDB;
+        const uint8_t *bs = Bs + (cur * BN + wn * (BN / 2) + gi) * S::LDB;
+#pragma unroll
+        for (int s = 0; s < BK / 32; ++s) {
+            const int kb = (s * 32 + 8 * gg) * (int)sizeof(T);
+            F fa[S::MB], fb[S::NB];
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m) fa[m] = *(const F *)(as + m * 16 * S::LDB + kb);
+#pragma unroll
+            for (int n = 0; n < S::NB; ++n) fb[n] = *(const F *)(bs + n * 16 * S::LDB + kb);
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                for (int n = 0; n < S::NB; ++n) acc[m][n] = RM<KIND>::mfma(fa[m], fb[n], acc[m][n]);
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+}
+
+}  // namespace mpc

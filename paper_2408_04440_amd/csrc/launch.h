@@ -1,0 +1,74 @@
+// Host-side launchers of the mpchol kernels (all enqueue on `st`, no sync).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mpc {
+
+// Where the tiles live (device pointers), passed to kernels by value.
+struct Tiles {
+    char *slots;          // packed lower tiles, tile_index(I,J) * slot_bytes
+    int64_t slot_bytes;   // b*b*8
+    int b, nt;
+    int64_t n;
+    const uint8_t *map;   // nt*nt classes, entry I + J*nt
+    int32_t *tscale;      // nt*nt stored scale exponents
+    int lo16;
+};
+
+// Source of Sigma: the generator (sigma, x, rho, nugget) or a kept FP64 copy
+// in the packed tile layout (orig != nullptr).
+struct Source {
+    const double *sigma, *x;
+    double rho, nugget;
+    const double *orig;
+};
+
+// Panel copies of the current step: one b*b buffer per panel row tile I.
+struct Panel {
+    double *p64;      // column-major
+    float *p32;       // column-major
+    uint16_t *p16;    // row-major (k contiguous)
+    uint8_t *p8;      // row-major (k contiguous)
+    unsigned long long *pmax;  // nt: max |X| of the TRSM output of tile I (FP64 bits)
+    int32_t *pscale;           // nt*4: scale exponent of the class-q copy of tile I
+};
+
+// ---- tiles (k_tiles.hip)
+void launch_norms(const Tiles &T, const Source &S, double *fro2, double *amax, hipStream_t st);
+void launch_load(const Tiles &T, const Source &S, hipStream_t st);
+void launch_copy_matrix(const Tiles &T, const double *A, int64_t lda, double *orig, hipStream_t st);
+void launch_panel_max(const Tiles &T, const Panel &P, int k, hipStream_t st);
+void launch_convert(const Tiles &T, const Panel &P, int k, const uint8_t *qmask, hipStream_t st);
+void launch_logdet(const Tiles &T, double *out, hipStream_t st);
+void launch_get_factor(const Tiles &T, double *L, int64_t ldl, hipStream_t st);
+void launch_zero_upper_diag(const Tiles &T, int k, hipStream_t st);
+
+// ---- factorization (k_factor.hip)
+void launch_potrf_tile(const Tiles &T, int k, unsigned long long *info, hipStream_t st);
+void launch_trsm_panel(const Tiles &T, const Panel &P, int k, hipStream_t st);
+// grouped update A_IJ -= L_Ik L_Jk^T of class q over `nitems` packed (I << 16 | J) items
+void launch_update(const Tiles &T, const Panel &P, int q, const int32_t *items, int nitems, hipStream_t st);
+
+// ---- residual (k_residual.hip): items = every lower tile as (I << 16 | J);
+// partial = scratch of nitems * (b/128)^2 doubles; tile_res2 = nt*nt output
+void launch_residual_items(const Tiles &T, const Source &S, const int32_t *items, int nitems, double *partial,
+                           double *tile_res2, hipStream_t st);
+
+// ---- solve, sample (k_apply.hip)
+void launch_solve(const Tiles &T, double *B, int64_t ldb, int nrhs, hipStream_t st);
+void launch_normal_draws(uint64_t seed, int64_t count, float *z, uint32_t *raw, hipStream_t st);
+void launch_normal_matrix(uint64_t seed, int64_t n, int ndraws, float *Z, int64_t ldz, hipStream_t st);
+void launch_lower_apply(const Tiles &T, const float *Z, int64_t ldz, float *Y, int64_t ldy, int ndraws, hipStream_t st);
+
+// ---- selector (k_mlp.hip)
+void launch_features(const Tiles &T, const double *fro2, const double *amax, double total, double eps, float *feats,
+                     hipStream_t st);
+void launch_mlp_infer_map(const Tiles &T, const float *params, const float *feats, int band, unsigned allowed,
+                          uint8_t *map_out, hipStream_t st);
+void launch_mlp_forward(const float *params, const float *X, int64_t nb, float *logits, int32_t *cls, hipStream_t st);
+void launch_mlp_grad(const float *params, const float *X, const int32_t *y, int64_t nb, const float *cw, float alpha,
+                     float *grad, float *loss, float *partials, hipStream_t st);
+void launch_adam(float *params, const float *grad, float *m, float *v, int64_t np, int step, float lr, hipStream_t st);
+
+}  // namespace mpc

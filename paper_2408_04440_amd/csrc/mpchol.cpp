@@ -1,0 +1,870 @@
+// Host runtime of libmpchol: handle state, tile storage, the precision-map
+// rules, the static per-step schedule of the right-looking tile algorithm
+// (Sec. V.A) and the C ABI declared in include/mpchol.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mpchol.h"
+#include "common.h"
+#include "launch.h"
+
+using namespace mpc;
+
+namespace {
+
+enum State { S_CREATED = 0, S_SOURCE = 1, S_LOADED = 2, S_FACTORED = 3, S_FAILED = 4 };
+
+double unit_roundoff(int q, int lo16)
+{
+    switch (q) {
+    case P32: return std::ldexp(1.0, -24);
+    case P16: return lo16 == LO16_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -11);
+    case P8: return std::ldexp(1.0, -4);
+    default: return std::ldexp(1.0, -53);
+    }
+}
+
+}  // namespace
+
+struct mpchol_handle {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    mpchol_opts o{};
+    int64_t n = 0;
+    int b = 0, nt = 0;
+    int64_t ntile = 0;
+    size_t slot_bytes = 0;
+    char *slots = nullptr;
+    double *orig = nullptr;
+    double *d_sigma = nullptr, *d_x = nullptr;
+    double rho = 0, nugget = 0;
+    int src = 0;  // 0 none, 1 matrix, 2 generator
+    // panel copies
+    double *p64 = nullptr;
+    float *p32 = nullptr;
+    uint16_t *p16 = nullptr;
+    uint8_t *p8 = nullptr;
+    unsigned long long *pmax = nullptr;
+    int32_t *pscale = nullptr;
+    // per-tile metadata
+    uint8_t *d_map = nullptr;
+    int32_t *d_tscale = nullptr;
+    double *d_fro2 = nullptr, *d_amax = nullptr;
+    unsigned long long *d_info = nullptr;
+    double *d_scalar = nullptr;
+    std::vector<uint8_t> h_map;
+    std::vector<double> h_fro2, h_amax;
+    double total_fro = 0;
+    double last_eps = 1e-9;
+    // schedule
+    int32_t *d_items = nullptr;
+    std::vector<int64_t> item_off;  // (nt * 4 + 1) offsets, step-major, class-minor
+    uint8_t *d_qmask = nullptr;
+    int32_t *d_all_items = nullptr;  // every lower tile, for the residual
+    double *d_partial = nullptr, *d_tres2 = nullptr;
+    // selector
+    float *d_params = nullptr, *d_feats = nullptr;
+    bool have_params = false;
+    int state = S_CREATED;
+    int rule_used = MPCHOL_RULE_FP64;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> gev;  // profile mode: start/stop pairs per update launch
+    std::vector<int> gev_class;
+    std::vector<double> gev_flops;
+    mpchol_stats stats{};
+
+    Tiles tiles() const
+    {
+        Tiles T;
+        T.slots = slots;
+        T.slot_bytes = (int64_t)slot_bytes;
+        T.b = b;
+        T.nt = nt;
+        T.n = n;
+        T.map = d_map;
+        T.tscale = d_tscale;
+        T.lo16 = o.lo16;
+        return T;
+    }
+    Source source() const
+    {
+        Source S;
+        S.sigma = d_sigma;
+        S.x = d_x;
+        S.rho = rho;
+        S.nugget = nugget;
+        S.orig = orig;
+        return S;
+    }
+    Panel panel() const
+    {
+        Panel P;
+        P.p64 = p64;
+        P.p32 = p32;
+        P.p16 = p16;
+        P.p8 = p8;
+        P.pmax = pmax;
+        P.pscale = pscale;
+        return P;
+    }
+};
+
+#define HIPCHK(x)                                      \
+    do {                                               \
+        if ((x) != hipSuccess) return MPCHOL_EHIP;     \
+    } while (0)
+
+template <typename T>
+static int dalloc(T **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) return MPCHOL_OK;
+    if (hipMalloc((void **)p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return MPCHOL_ENOMEM;
+    }
+    return MPCHOL_OK;
+}
+
+static void release(mpchol_handle *h)
+{
+    void *ptrs[] = {h->slots, h->orig, h->d_sigma, h->d_x, h->p64, h->p32, h->p16, h->p8, h->pmax, h->pscale,
+                    h->d_map, h->d_tscale, h->d_fro2, h->d_amax, h->d_info, h->d_scalar, h->d_items, h->d_qmask,
+                    h->d_all_items, h->d_partial, h->d_tres2, h->d_params, h->d_feats};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : h->gev) (void)hipEventDestroy(e);
+}
+
+extern "C" {
+
+void mpchol_default_opts(mpchol_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->stream = nullptr;
+    o->lo16 = MPCHOL_LO16_F16;
+    o->band = 1;
+    o->allowed = 0xF;
+    o->band_variant = MPCHOL_BAND_DP_HP;
+    o->verify = 0;
+    o->verify_eps = 1e-9;
+    o->profile = 0;
+}
+
+const char *mpchol_strerror(int s)
+{
+    switch (s) {
+    case MPCHOL_OK: return "ok";
+    case MPCHOL_NOT_SPD: return "matrix not positive definite (a pivot was not positive)";
+    case MPCHOL_EINVAL: return "invalid argument";
+    case MPCHOL_ENOMEM: return "device allocation failed";
+    case MPCHOL_EHIP: return "HIP runtime error";
+    case MPCHOL_EORDER: return "call out of order";
+    case MPCHOL_EBUDGET: return "backward-error budget missed after every fallback";
+    case MPCHOL_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
+{
+    if (!hp) return MPCHOL_EINVAL;
+    *hp = nullptr;
+    if (n <= 0 || tile < 128 || tile > 2048 || tile % 128 != 0) return MPCHOL_EINVAL;
+    int64_t nt = (n + tile - 1) / tile;
+    if (nt > 32767) return MPCHOL_EINVAL;
+    mpchol_opts opt;
+    if (o) opt = *o;
+    else mpchol_default_opts(&opt);
+    if (opt.lo16 != MPCHOL_LO16_F16 && opt.lo16 != MPCHOL_LO16_BF16) return MPCHOL_EINVAL;
+    if (opt.band < 0) return MPCHOL_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opt.device < 0 || opt.device >= ndev) {
+        (void)hipGetLastError();
+        return MPCHOL_EHIP;
+    }
+    if (hipSetDevice(opt.device) != hipSuccess) return MPCHOL_EHIP;
+
+    mpchol_handle *h = new (std::nothrow) mpchol_handle();
+    if (!h) return MPCHOL_ENOMEM;
+    h->dev = opt.device;
+    h->st = (hipStream_t)opt.stream;
+    h->o = opt;
+    h->n = n;
+    h->b = tile;
+    h->nt = (int)nt;
+    h->ntile = nt * (nt + 1) / 2;
+    h->slot_bytes = (size_t)tile * tile * 8;
+    const size_t bb = (size_t)tile * tile;
+    int rc = MPCHOL_OK;
+    auto A = [&](int r) {
+        if (rc == MPCHOL_OK && r != MPCHOL_OK) rc = r;
+    };
+    A(dalloc(&h->slots, h->ntile * h->slot_bytes));
+    A(dalloc(&h->p64, nt * bb * 8));
+    A(dalloc(&h->p32, nt * bb * 4));
+    A(dalloc(&h->p16, nt * bb * 2));
+    A(dalloc(&h->p8, nt * bb));
+    A(dalloc(&h->pmax, nt * 8));
+    A(dalloc(&h->pscale, nt * 4 * 4));
+    A(dalloc(&h->d_map, nt * nt));
+    A(dalloc(&h->d_tscale, nt * nt * 4));
+    A(dalloc(&h->d_fro2, nt * nt * 8));
+    A(dalloc(&h->d_amax, nt * nt * 8));
+    A(dalloc(&h->d_info, 8));
+    A(dalloc(&h->d_scalar, 64));
+    A(dalloc(&h->d_qmask, nt * nt));
+    A(dalloc(&h->d_all_items, h->ntile * 4));
+    A(dalloc(&h->d_partial, h->ntile * (bb / (128 * 128)) * 8));
+    A(dalloc(&h->d_tres2, nt * nt * 8));
+    A(dalloc(&h->d_params, MPCHOL_MLP_NPARAM * 4));
+    A(dalloc(&h->d_feats, nt * nt * 8 * 4));
+    for (auto &e : h->ev)
+        if (rc == MPCHOL_OK && hipEventCreate(&e) != hipSuccess) rc = MPCHOL_EHIP;
+    if (rc == MPCHOL_OK) {
+        std::vector<int32_t> all;
+        all.reserve(h->ntile);
+        for (int I = 0; I < nt; ++I)
+            for (int J = 0; J <= I; ++J) all.push_back((I << 16) | J);
+        if (hipMemcpy(h->d_all_items, all.data(), all.size() * 4, hipMemcpyHostToDevice) != hipSuccess) rc = MPCHOL_EHIP;
+        if (hipMemset(h->d_tscale, 0, nt * nt * 4) != hipSuccess) rc = MPCHOL_EHIP;
+        if (hipMemset(h->d_map, 0, nt * nt) != hipSuccess) rc = MPCHOL_EHIP;
+    }
+    if (rc != MPCHOL_OK) {
+        release(h);
+        delete h;
+        return rc;
+    }
+    h->h_map.assign(nt * nt, 0);
+    h->stats.n = n;
+    h->stats.tile = tile;
+    h->stats.nt = (int)nt;
+    *hp = h;
+    return MPCHOL_OK;
+}
+
+int mpchol_destroy(mpchol_t h)
+{
+    if (!h) return MPCHOL_OK;
+    (void)hipSetDevice(h->dev);
+    (void)hipStreamSynchronize(h->st);
+    release(h);
+    delete h;
+    return MPCHOL_OK;
+}
+
+int mpchol_set_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_device)
+{
+    if (!h || !A || lda < h->n) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    if (!h->orig) {
+        int rc = dalloc(&h->orig, h->ntile * h->slot_bytes);
+        if (rc) return rc;
+    }
+    const double *dA = A;
+    double *tmp = nullptr;
+    if (!on_device) {
+        size_t bytes = (size_t)lda * h->n * 8;
+        int rc = dalloc(&tmp, bytes);
+        if (rc) return rc;
+        if (hipMemcpyAsync(tmp, A, bytes, hipMemcpyHostToDevice, h->st) != hipSuccess) {
+            (void)hipFree(tmp);
+            return MPCHOL_EHIP;
+        }
+        dA = tmp;
+    }
+    launch_copy_matrix(h->tiles(), dA, lda, h->orig, h->st);
+    hipError_t e = hipStreamSynchronize(h->st);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess || hipGetLastError() != hipSuccess) return MPCHOL_EHIP;
+    h->src = 1;
+    h->state = S_SOURCE;
+    return MPCHOL_OK;
+}
+
+int mpchol_set_generator(mpchol_t h, const double *sigma, const double *x, double rho, double nugget)
+{
+    if (!h || !sigma || !x || !(rho > 0) || !(nugget >= 0)) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    if (!h->d_sigma) {
+        int rc = dalloc(&h->d_sigma, h->n * 8);
+        if (rc) return rc;
+        rc = dalloc(&h->d_x, h->n * 8);
+        if (rc) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(h->d_sigma, sigma, h->n * 8, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(h->d_x, x, h->n * 8, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (h->orig) {
+        (void)hipFree(h->orig);
+        h->orig = nullptr;
+    }
+    h->rho = rho;
+    h->nugget = nugget;
+    h->src = 2;
+    h->state = S_SOURCE;
+    return MPCHOL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- map rules
+static void rule_fp64(mpchol_handle *h, std::vector<uint8_t> &m) { std::fill(m.begin(), m.end(), (uint8_t)P64); }
+
+static void rule_norm(mpchol_handle *h, double eps, std::vector<uint8_t> &m)
+{
+    const int nt = h->nt;
+    const double thr = eps * h->total_fro / nt;
+    for (int J = 0; J < nt; ++J)
+        for (int I = 0; I < nt; ++I) {
+            uint8_t c = P64;
+            if (I > J && I - J > h->o.band) {
+                double f = std::sqrt(h->h_fro2[I + (size_t)J * nt]);
+                for (int cls = P8; cls >= P32; --cls) {
+                    if (!(h->o.allowed & (1u << cls))) continue;
+                    if (f * unit_roundoff(cls, h->o.lo16) <= thr) {
+                        c = (uint8_t)cls;
+                        break;
+                    }
+                }
+            }
+            m[I + (size_t)J * nt] = (I >= J) ? c : 0;
+        }
+}
+
+// Highest allowed class at or above (more precise than) `c`.
+static uint8_t clamp_allowed(uint32_t allowed, int c)
+{
+    while (c > P64 && !(allowed & (1u << c))) --c;
+    return (uint8_t)c;
+}
+
+static void rule_band(mpchol_handle *h, std::vector<uint8_t> &m)
+{
+    const int nt = h->nt, w = h->o.band;
+    int w32 = w;
+    if (h->o.band_variant == MPCHOL_BAND_DP_SP_HP) {
+        // narrowest band beyond the FP64 band holding >= 5% of the strict-lower tiles
+        const double total = (double)nt * (nt - 1) / 2.0;
+        double cnt = 0;
+        w32 = w;
+        while (w32 < nt - 1 && cnt < 0.05 * total) {
+            ++w32;
+            if (w32 > w) cnt += (double)(nt - w32);
+        }
+    }
+    for (int J = 0; J < nt; ++J)
+        for (int I = 0; I < nt; ++I) {
+            int c = P64;
+            int d = I - J;
+            if (I > J && d > w) {
+                switch (h->o.band_variant) {
+                case MPCHOL_BAND_DP_SP: c = P32; break;
+                case MPCHOL_BAND_DP_SP_HP: c = (d <= w32) ? P32 : P16; break;
+                default: c = P16; break;
+                }
+                c = clamp_allowed(h->o.allowed, c);
+            }
+            m[I + (size_t)J * nt] = (I >= J) ? (uint8_t)c : 0;
+        }
+}
+
+static void build_schedule_counts(mpchol_handle *h, std::vector<int32_t> &items, std::vector<uint8_t> &qmask)
+{
+    const int nt = h->nt;
+    h->item_off.assign((size_t)nt * 4 + 1, 0);
+    items.clear();
+    for (int k = 0; k < nt; ++k)
+        for (int q = 0; q < 4; ++q) {
+            h->item_off[(size_t)k * 4 + q] = (int64_t)items.size();
+            for (int J = k + 1; J < nt; ++J)
+                for (int I = J; I < nt; ++I) {
+                    int c = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
+                    if (c == q) items.push_back((I << 16) | J);
+                }
+        }
+    h->item_off[(size_t)nt * 4] = (int64_t)items.size();
+    qmask.assign((size_t)nt * nt, 0);
+    for (int k = 0; k < nt; ++k)
+        for (int I = k + 1; I < nt; ++I) {
+            uint8_t msk = 1;  // SYRK(I,I) reads the FP64 copy
+            for (int J = k + 1; J < I; ++J) msk |= (uint8_t)(1u << h->h_map[I + (size_t)J * nt]);
+            for (int J = I + 1; J < nt; ++J) msk |= (uint8_t)(1u << h->h_map[J + (size_t)I * nt]);
+            qmask[I + (size_t)k * nt] = msk;
+        }
+}
+
+static void fill_flop_stats(mpchol_handle *h)
+{
+    const int nt = h->nt;
+    const double b3 = (double)h->b * h->b * h->b;
+    for (int q = 0; q < 4; ++q) {
+        h->stats.tiles_per_class[q] = 0;
+        h->stats.flops_per_class[q] = 0;
+    }
+    for (int J = 0; J < nt; ++J) {
+        h->stats.flops_per_class[P64] += b3 / 3.0 + (double)(nt - J - 1) * b3;  // POTRF + TRSM below it
+        h->stats.flops_per_class[P64] += (double)J * b3;                            // SYRK updates of (J,J)
+        for (int I = J + 1; I < nt; ++I) {
+            int c = h->h_map[I + (size_t)J * nt];
+            h->stats.tiles_per_class[c] += 1;
+            h->stats.flops_per_class[c] += 2.0 * b3 * J;  // GEMM updates of (I,J), one per k < J
+        }
+    }
+}
+
+// Host-side map from norms by rule, then upload map + schedule and load.
+static int apply_map(mpchol_handle *h, int rule, double eps, const uint8_t *user_map)
+{
+    const int nt = h->nt;
+    std::vector<uint8_t> m((size_t)nt * nt, 0);
+    switch (rule) {
+    case MPCHOL_RULE_FP64: rule_fp64(h, m); break;
+    case MPCHOL_RULE_NORM: rule_norm(h, eps, m); break;
+    case MPCHOL_RULE_BAND: rule_band(h, m); break;
+    case MPCHOL_RULE_USER:
+        for (int J = 0; J < nt; ++J)
+            for (int I = 0; I < nt; ++I) {
+                uint8_t c = user_map[I + (size_t)J * nt];
+                if (c > P8) return MPCHOL_EINVAL;
+                m[I + (size_t)J * nt] = (I > J) ? clamp_allowed(h->o.allowed, c) : 0;
+            }
+        break;
+    case MPCHOL_RULE_LEARNED: {
+        Tiles T = h->tiles();
+        T.map = h->d_map;
+        launch_features(T, h->d_fro2, h->d_amax, h->total_fro, eps, h->d_feats, h->st);
+        launch_mlp_infer_map(T, h->d_params, h->d_feats, h->o.band, h->o.allowed, h->d_map, h->st);
+        HIPCHK(hipMemcpyAsync(m.data(), h->d_map, m.size(), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        break;
+    }
+    default: return MPCHOL_EINVAL;
+    }
+    h->h_map = m;
+    std::vector<int32_t> items;
+    std::vector<uint8_t> qmask;
+    build_schedule_counts(h, items, qmask);
+    if (h->d_items) (void)hipFree(h->d_items);
+    h->d_items = nullptr;
+    if (!items.empty()) {
+        int rc = dalloc(&h->d_items, items.size() * 4);
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(h->d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice, h->st));
+    }
+    HIPCHK(hipMemcpyAsync(h->d_map, m.data(), m.size(), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(h->d_qmask, qmask.data(), qmask.size(), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemsetAsync(h->d_tscale, 0, (size_t)nt * nt * 4, h->st));
+    launch_load(h->tiles(), h->source(), h->st);
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    h->rule_used = rule;
+    fill_flop_stats(h);
+    h->state = S_LOADED;
+    return MPCHOL_OK;
+}
+
+static int compute_norms(mpchol_handle *h)
+{
+    const int nt = h->nt;
+    HIPCHK(hipMemsetAsync(h->d_fro2, 0, (size_t)nt * nt * 8, h->st));
+    HIPCHK(hipMemsetAsync(h->d_amax, 0, (size_t)nt * nt * 8, h->st));
+    launch_norms(h->tiles(), h->source(), h->d_fro2, h->d_amax, h->st);
+    h->h_fro2.assign((size_t)nt * nt, 0.0);
+    h->h_amax.assign((size_t)nt * nt, 0.0);
+    HIPCHK(hipMemcpyAsync(h->h_fro2.data(), h->d_fro2, (size_t)nt * nt * 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipMemcpyAsync(h->h_amax.data(), h->d_amax, (size_t)nt * nt * 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    double tot = 0.0;
+    for (int J = 0; J < nt; ++J)
+        for (int I = J; I < nt; ++I) tot += (I == J ? 1.0 : 2.0) * h->h_fro2[I + (size_t)J * nt];
+    h->total_fro = std::sqrt(tot);
+    h->stats.total_fro = h->total_fro;
+    return MPCHOL_OK;
+}
+
+static int run_factor(mpchol_handle *h, int64_t *info);
+static int residual(mpchol_handle *h, double *berr, double *tile_res2);
+
+extern "C" int mpchol_precision_map(mpchol_t h, int32_t rule, double eps, const uint8_t *user_map, uint8_t *map_out)
+{
+    if (!h) return MPCHOL_EINVAL;
+    if (h->state < S_SOURCE) return MPCHOL_EORDER;
+    if (rule < MPCHOL_RULE_FP64 || rule > MPCHOL_RULE_LEARNED) return MPCHOL_EINVAL;
+    if (rule == MPCHOL_RULE_USER && !user_map) return MPCHOL_EINVAL;
+    if (rule == MPCHOL_RULE_LEARNED && !h->have_params) return MPCHOL_EORDER;
+    if ((rule == MPCHOL_RULE_NORM || rule == MPCHOL_RULE_LEARNED) && !(eps > 0)) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipEventRecord(h->ev[2], h->st));
+    int rc = compute_norms(h);
+    if (rc) return rc;
+    h->last_eps = eps;
+    rc = apply_map(h, rule, eps, user_map);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(h->ev[3], h->st));
+    HIPCHK(hipEventSynchronize(h->ev[3]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
+    h->stats.t_map_ms = ms;
+    if (map_out) std::memcpy(map_out, h->h_map.data(), h->h_map.size());
+    return MPCHOL_OK;
+}
+
+static int run_factor(mpchol_handle *h, int64_t *info)
+{
+    const int nt = h->nt;
+    Tiles T = h->tiles();
+    Panel P = h->panel();
+    for (auto e : h->gev) (void)hipEventDestroy(e);
+    h->gev.clear();
+    h->gev_class.clear();
+    h->gev_flops.clear();
+    HIPCHK(hipMemsetAsync(h->d_info, 0xFF, 8, h->st));
+    HIPCHK(hipEventRecord(h->ev[0], h->st));
+    const double b3 = (double)h->b * h->b * h->b;
+    for (int k = 0; k < nt; ++k) {
+        launch_potrf_tile(T, k, h->d_info, h->st);
+        if (k == nt - 1) break;
+        launch_trsm_panel(T, P, k, h->st);
+        HIPCHK(hipMemsetAsync(h->pmax, 0, (size_t)nt * 8, h->st));
+        launch_panel_max(T, P, k, h->st);
+        launch_convert(T, P, k, h->d_qmask + (size_t)k * nt, h->st);
+        for (int q = 0; q < 4; ++q) {
+            int64_t off = h->item_off[(size_t)k * 4 + q];
+            int cnt = (int)(h->item_off[(size_t)k * 4 + q + 1] - off);
+            if (cnt <= 0) continue;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (h->o.profile) {
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                HIPCHK(hipEventRecord(e0, h->st));
+            }
+            launch_update(T, P, q, h->d_items + off, cnt, h->st);
+            if (h->o.profile) {
+                HIPCHK(hipEventRecord(e1, h->st));
+                h->gev.push_back(e0);
+                h->gev.push_back(e1);
+                h->gev_class.push_back(q);
+                h->gev_flops.push_back(2.0 * b3 * cnt);
+            }
+        }
+    }
+    HIPCHK(hipEventRecord(h->ev[1], h->st));
+    unsigned long long hinfo = 0;
+    HIPCHK(hipMemcpyAsync(&hinfo, h->d_info, 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    h->stats.t_factor_ms = ms;
+    for (int q = 0; q < 4; ++q) {
+        h->stats.t_gemm_ms[q] = 0;
+        h->stats.gemm_launches[q] = 0;
+        h->stats.gemm_flops[q] = 0;
+    }
+    for (size_t i = 0; i < h->gev_class.size(); ++i) {
+        float g = 0;
+        HIPCHK(hipEventElapsedTime(&g, h->gev[2 * i], h->gev[2 * i + 1]));
+        int q = h->gev_class[i];
+        h->stats.t_gemm_ms[q] += g;
+        h->stats.gemm_launches[q] += 1;
+        h->stats.gemm_flops[q] += h->gev_flops[i];
+    }
+    h->stats.rule_used = h->rule_used;
+    int64_t inf = (hinfo == ~0ull) ? 0 : (int64_t)hinfo;
+    if (info) *info = inf;
+    if (inf) {
+        h->state = S_FAILED;
+        return MPCHOL_NOT_SPD;
+    }
+    h->state = S_FACTORED;
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_factor(mpchol_t h, int64_t *info)
+{
+    if (!h) return MPCHOL_EINVAL;
+    if (info) *info = 0;
+    if (h->state != S_LOADED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    h->stats.fallbacks = 0;
+    int64_t inf = 0;
+    int rc = run_factor(h, &inf);
+    if (rc < 0) return rc;
+    if (h->rule_used == MPCHOL_RULE_LEARNED && h->o.verify) {
+        const int fallback_rules[2] = {MPCHOL_RULE_NORM, MPCHOL_RULE_FP64};
+        for (int f = 0;; ++f) {
+            bool ok = (rc == MPCHOL_OK);
+            if (ok) {
+                double be = 0;
+                int r2 = residual(h, &be, nullptr);
+                if (r2) return r2;
+                ok = (be <= h->o.verify_eps);
+            }
+            if (ok) break;
+            if (f >= 2) {
+                if (info) *info = inf;
+                return rc == MPCHOL_NOT_SPD ? MPCHOL_NOT_SPD : MPCHOL_EBUDGET;
+            }
+            h->stats.fallbacks += 1;
+            int r3 = apply_map(h, fallback_rules[f], h->last_eps, nullptr);
+            if (r3) return r3;
+            rc = run_factor(h, &inf);
+            if (rc < 0) return rc;
+        }
+    }
+    if (info) *info = inf;
+    return rc;
+}
+
+extern "C" int mpchol_logdet(mpchol_t h, double *out)
+{
+    if (!h || !out) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    launch_logdet(h->tiles(), h->d_scalar, h->st);
+    HIPCHK(hipMemcpyAsync(out, h->d_scalar, 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_get_factor(mpchol_t h, double *L, int64_t ldl)
+{
+    if (!h || !L || ldl < h->n) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    launch_get_factor(h->tiles(), L, ldl, h->st);
+    HIPCHK(hipGetLastError());
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_get_tile_scales(mpchol_t h, int32_t *t)
+{
+    if (!h || !t) return MPCHOL_EINVAL;
+    if (h->state < S_LOADED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipMemcpyAsync(t, h->d_tscale, (size_t)h->nt * h->nt * 4, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return MPCHOL_OK;
+}
+
+static int residual(mpchol_handle *h, double *berr, double *tile_res2)
+{
+    const int nt = h->nt;
+    HIPCHK(hipEventRecord(h->ev[2], h->st));
+    launch_residual_items(h->tiles(), h->source(), h->d_all_items, (int)h->ntile, h->d_partial, h->d_tres2, h->st);
+    std::vector<double> r((size_t)nt * nt, 0.0);
+    HIPCHK(hipMemsetAsync(h->d_scalar, 0, 8, h->st));
+    HIPCHK(hipMemcpyAsync(r.data(), h->d_tres2, r.size() * 8, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipEventRecord(h->ev[3], h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
+    h->stats.t_residual_ms = ms;
+    double tot = 0.0;
+    for (int J = 0; J < nt; ++J)
+        for (int I = J; I < nt; ++I) tot += (I == J ? 1.0 : 2.0) * r[I + (size_t)J * nt];
+    if (berr) *berr = std::sqrt(tot) / h->total_fro;
+    if (tile_res2) {
+        for (int J = 0; J < nt; ++J)
+            for (int I = 0; I < nt; ++I) tile_res2[I + (size_t)J * nt] = (I >= J) ? r[I + (size_t)J * nt] : 0.0;
+    }
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2)
+{
+    if (!h || !berr) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    return residual(h, berr, tile_res2);
+}
+
+extern "C" int mpchol_get_stats(mpchol_t h, mpchol_stats *s)
+{
+    if (!h || !s) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipStreamSynchronize(h->st));
+    *s = h->stats;
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_solve(mpchol_t h, int32_t nrhs, double *B, int64_t ldb)
+{
+    if (!h || !B || nrhs <= 0 || ldb < h->n) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipEventRecord(h->ev[2], h->st));
+    launch_solve(h->tiles(), B, ldb, nrhs, h->st);
+    HIPCHK(hipEventRecord(h->ev[3], h->st));
+    HIPCHK(hipGetLastError());
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_sample_z(mpchol_t h, int32_t ndraws, const float *Z, int64_t ldz, float *Y, int64_t ldy)
+{
+    if (!h || !Z || !Y || ndraws <= 0 || ldz < h->n || ldy < h->n) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    launch_lower_apply(h->tiles(), Z, ldz, Y, ldy, ndraws, h->st);
+    HIPCHK(hipGetLastError());
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_sample(mpchol_t h, int32_t ndraws, uint64_t seed, float *Y, int64_t ldy)
+{
+    if (!h || !Y || ndraws <= 0 || ldy < h->n) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    float *Z = nullptr;
+    int rc = dalloc(&Z, (size_t)h->n * ndraws * 4);
+    if (rc) return rc;
+    launch_normal_matrix(seed, h->n, ndraws, Z, h->n, h->st);
+    launch_lower_apply(h->tiles(), Z, h->n, Y, ldy, ndraws, h->st);
+    hipError_t e = hipStreamSynchronize(h->st);
+    (void)hipFree(Z);
+    if (e != hipSuccess || hipGetLastError() != hipSuccess) return MPCHOL_EHIP;
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_normal_draws(mpchol_t h, int64_t count, uint64_t seed, float *z, uint32_t *raw)
+{
+    if (!h || count <= 0 || (!z && !raw)) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    launch_normal_draws(seed, count, z, raw, h->st);
+    HIPCHK(hipGetLastError());
+    return MPCHOL_OK;
+}
+
+// ---------------------------------------------------------------- selector
+extern "C" int mpchol_selector_set(mpchol_t h, const float *params, int64_t nparam)
+{
+    if (!h || !params || nparam != MPCHOL_MLP_NPARAM) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    HIPCHK(hipMemcpyAsync(h->d_params, params, nparam * 4, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    h->have_params = true;
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_selector_features(mpchol_t h, double eps, float *feats)
+{
+    if (!h || !feats || !(eps > 0)) return MPCHOL_EINVAL;
+    if (h->state < S_LOADED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    launch_features(h->tiles(), h->d_fro2, h->d_amax, h->total_fro, eps, h->d_feats, h->st);
+    HIPCHK(hipMemcpyAsync(feats, h->d_feats, (size_t)h->nt * h->nt * 8 * 4, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    return MPCHOL_OK;
+}
+
+// Greedy per-tile lowering under a measured backward-error budget.
+extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out)
+{
+    if (!h || !labels || !(eps > 0)) return MPCHOL_EINVAL;
+    if (h->state < S_SOURCE) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    const int nt = h->nt, w = h->o.band;
+    int rc = compute_norms(h);
+    if (rc) return rc;
+    const double budget = 0.5 * (eps * h->total_fro) * (eps * h->total_fro);
+    // per-tile squared residual at each class: factor with every eligible tile at that class
+    std::vector<std::vector<double>> res(4, std::vector<double>((size_t)nt * nt, 0.0));
+    std::vector<uint8_t> um((size_t)nt * nt, 0);
+    for (int q = P32; q <= P8; ++q) {
+        if (!(h->o.allowed & (1u << q))) continue;
+        for (int J = 0; J < nt; ++J)
+            for (int I = J + 1; I < nt; ++I) um[I + (size_t)J * nt] = (I - J > w) ? (uint8_t)q : 0;
+        rc = apply_map(h, MPCHOL_RULE_USER, eps, um.data());
+        if (rc) return rc;
+        int64_t inf = 0;
+        rc = run_factor(h, &inf);
+        if (rc < 0) return rc;
+        if (rc == MPCHOL_NOT_SPD) {
+            for (auto &v : res[q]) v = INFINITY;  // a breakdown marks this class unusable everywhere
+            continue;
+        }
+        double be = 0;
+        rc = residual(h, &be, res[q].data());
+        if (rc) return rc;
+    }
+    // greedy: time weight of tile (I,J) = J updates of 2b^3 flops at the class's MFMA rate
+    const double rate[4] = {78.6, 157.3, 2500.0, 5000.0};
+    std::vector<uint8_t> cur((size_t)nt * nt, 0);
+    double used = 0.0;
+    struct Move {
+        double ratio;
+        int I, J, q;
+    };
+    for (;;) {
+        Move best{-1.0, -1, -1, -1};
+        for (int J = 0; J < nt; ++J)
+            for (int I = J + w + 1; I < nt; ++I) {
+                size_t t = I + (size_t)J * nt;
+                int c = cur[t];
+                for (int q = c + 1; q <= P8; ++q) {
+                    if (!(h->o.allowed & (1u << q))) continue;
+                    double add = 2.0 * (res[q][t] - (c == 0 ? 0.0 : res[c][t]));
+                    if (!std::isfinite(add)) continue;
+                    if (used + std::max(add, 0.0) > budget) continue;
+                    double saved = (double)J * (1.0 / rate[c] - 1.0 / rate[q]);
+                    double ratio = saved / std::max(add, 1e-300);
+                    if (ratio > best.ratio) best = Move{ratio, I, J, q};
+                }
+            }
+        if (best.I < 0) break;
+        size_t t = best.I + (size_t)best.J * nt;
+        int c = cur[t];
+        used += 2.0 * (res[best.q][t] - (c == 0 ? 0.0 : res[c][t]));
+        cur[t] = (uint8_t)best.q;
+    }
+    // verify; raise the worst tiles until the measured error fits
+    double be = INFINITY;
+    for (int it = 0; it < 64; ++it) {
+        rc = apply_map(h, MPCHOL_RULE_USER, eps, cur.data());
+        if (rc) return rc;
+        int64_t inf = 0;
+        rc = run_factor(h, &inf);
+        if (rc < 0) return rc;
+        std::vector<double> tr((size_t)nt * nt, 0.0);
+        if (rc == MPCHOL_OK) {
+            rc = residual(h, &be, tr.data());
+            if (rc) return rc;
+            if (be <= eps) break;
+        }
+        // raise the 5% of lowered tiles with the largest residual by one level
+        std::vector<std::pair<double, size_t>> v;
+        for (int J = 0; J < nt; ++J)
+            for (int I = J + 1; I < nt; ++I) {
+                size_t t = I + (size_t)J * nt;
+                if (cur[t] > P64) v.push_back({tr[t], t});
+            }
+        if (v.empty()) break;
+        std::sort(v.begin(), v.end(), [](auto &a, auto &b2) { return a.first > b2.first; });
+        size_t nr = std::max<size_t>(1, v.size() / 20);
+        for (size_t i = 0; i < nr; ++i) {
+            size_t t = v[i].second;
+            int c = cur[t] - 1;
+            while (c > P64 && !(h->o.allowed & (1u << c))) --c;
+            cur[t] = (uint8_t)c;
+        }
+    }
+    std::memcpy(labels, cur.data(), cur.size());
+    if (berr_out) *berr_out = be;
+    return MPCHOL_OK;
+}

@@ -1,0 +1,308 @@
+"""ctypes binding of libmpchol (include/mpchol.h): argument marshalling only.
+
+Every call goes straight to the C ABI of the HIP library; no arithmetic of
+the method happens here.  Device buffers are torch tensors (used for memory
+and streams only); host buffers are numpy arrays.  A missing library raises
+at import of the first call -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libmpchol.so")
+
+OK, NOT_SPD = 0, 1
+P64, P32, P16, P8 = 0, 1, 2, 3
+LO16_F16, LO16_BF16 = 0, 1
+RULE_FP64, RULE_NORM, RULE_BAND, RULE_USER, RULE_LEARNED = 0, 1, 2, 3, 4
+BAND_DP_SP, BAND_DP_SP_HP, BAND_DP_HP = 1, 2, 3
+MLP_NPARAM = 4996
+
+
+class MpcholError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+class Opts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("lo16", C.c_int32), ("band", C.c_int32),
+                ("allowed", C.c_uint32), ("band_variant", C.c_int32), ("verify", C.c_int32),
+                ("verify_eps", C.c_double), ("profile", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("tile", C.c_int32), ("nt", C.c_int32), ("tiles_per_class", C.c_int64 * 4),
+                ("flops_per_class", C.c_double * 4), ("total_fro", C.c_double), ("t_map_ms", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_sample_ms", C.c_double),
+                ("t_residual_ms", C.c_double), ("t_gemm_ms", C.c_double * 4), ("gemm_launches", C.c_int64 * 4),
+                ("gemm_flops", C.c_double * 4), ("fallbacks", C.c_int32), ("rule_used", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmpchol.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"libmpchol.so not built at {LIBPATH}: run __graft_entry__.build() "
+                              "or python paper_2408_04440_amd/build.py")
+        L = C.CDLL(LIBPATH)
+        vp, i32, i64, d, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64
+        sig = {
+            "mpchol_default_opts": (None, [C.POINTER(Opts)]),
+            "mpchol_create": (C.c_int, [C.POINTER(vp), i64, i32, C.POINTER(Opts)]),
+            "mpchol_destroy": (C.c_int, [vp]),
+            "mpchol_set_matrix": (C.c_int, [vp, vp, i64, i32]),
+            "mpchol_set_generator": (C.c_int, [vp, vp, vp, d, d]),
+            "mpchol_precision_map": (C.c_int, [vp, i32, d, vp, vp]),
+            "mpchol_factor": (C.c_int, [vp, C.POINTER(i64)]),
+            "mpchol_logdet": (C.c_int, [vp, C.POINTER(d)]),
+            "mpchol_solve": (C.c_int, [vp, i32, vp, i64]),
+            "mpchol_sample": (C.c_int, [vp, i32, u64, vp, i64]),
+            "mpchol_sample_z": (C.c_int, [vp, i32, vp, i64, vp, i64]),
+            "mpchol_normal_draws": (C.c_int, [vp, i64, u64, vp, vp]),
+            "mpchol_backward_error": (C.c_int, [vp, C.POINTER(d), vp]),
+            "mpchol_get_factor": (C.c_int, [vp, vp, i64]),
+            "mpchol_get_tile_scales": (C.c_int, [vp, vp]),
+            "mpchol_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
+            "mpchol_strerror": (C.c_char_p, [C.c_int]),
+            "mpchol_selector_set": (C.c_int, [vp, vp, i64]),
+            "mpchol_selector_features": (C.c_int, [vp, d, vp]),
+            "mpchol_selector_labels": (C.c_int, [vp, d, vp, C.POINTER(d)]),
+            "mpchol_mlp_create": (C.c_int, [C.POINTER(vp), i32, vp]),
+            "mpchol_mlp_destroy": (C.c_int, [vp]),
+            "mpchol_mlp_set_params": (C.c_int, [vp, vp, i64]),
+            "mpchol_mlp_get_params": (C.c_int, [vp, vp, i64]),
+            "mpchol_mlp_grad": (C.c_int, [vp, vp, vp, i64, vp, C.c_float, vp, C.POINTER(C.c_float)]),
+            "mpchol_mlp_train_step": (C.c_int, [vp, vp, vp, i64, vp, C.c_float, C.c_float, C.POINTER(C.c_float)]),
+            "mpchol_mlp_predict": (C.c_int, [vp, vp, i64, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().mpchol_strerror(int(status)).decode()
+
+
+def _chk(rc, where, allow_not_spd=False):
+    if rc < 0 or (rc == NOT_SPD and not allow_not_spd):
+        raise MpcholError(rc, where)
+    return rc
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _colmajor_ld(t, n):
+    """Leading dimension of a column-major 2-D tensor/array view (stride (1, ld))."""
+    if t.dim() == 1:
+        return max(n, t.shape[0])
+    s = t.stride()
+    if s[0] != 1:
+        raise ValueError("expected a column-major view (stride (1, ld)); pass X.T of a contiguous (cols, rows) tensor")
+    return s[1] if t.shape[1] > 1 else max(n, t.shape[0])
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        try:
+            import torch
+
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            return None
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------- handle
+def mpchol_default_opts() -> Opts:
+    o = Opts()
+    lib().mpchol_default_opts(C.byref(o))
+    return o
+
+
+def mpchol_create(n, tile, device=0, stream=None, lo16=LO16_F16, band=1, allowed=0xF, band_variant=BAND_DP_HP,
+                  verify=0, verify_eps=1e-9, profile=0):
+    o = mpchol_default_opts()
+    o.device, o.stream, o.lo16, o.band = device, _stream_ptr(stream), lo16, band
+    o.allowed, o.band_variant, o.verify, o.verify_eps, o.profile = allowed, band_variant, verify, verify_eps, profile
+    h = C.c_void_p()
+    _chk(lib().mpchol_create(C.byref(h), int(n), int(tile), C.byref(o)), "mpchol_create")
+    return h
+
+
+def mpchol_destroy(h):
+    _chk(lib().mpchol_destroy(h), "mpchol_destroy")
+
+
+def mpchol_set_matrix(h, A, n=None):
+    """A: torch float64 column-major view on the device, or a numpy array (host)."""
+    if isinstance(A, np.ndarray):
+        A = np.asfortranarray(A, dtype=np.float64)
+        rc = lib().mpchol_set_matrix(h, A.ctypes.data_as(C.c_void_p), A.shape[0], 0)
+    else:
+        rc = lib().mpchol_set_matrix(h, _ptr(A), _colmajor_ld(A, A.shape[0]), 1)
+    _chk(rc, "mpchol_set_matrix")
+
+
+def mpchol_set_generator(h, sigma, x, rho, nugget):
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    _chk(lib().mpchol_set_generator(h, sigma.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p), float(rho),
+                                    float(nugget)), "mpchol_set_generator")
+
+
+def mpchol_precision_map(h, rule, eps=1e-9, user_map=None, nt=None):
+    st = mpchol_get_stats(h) if nt is None else None
+    nt = nt if nt is not None else st["nt"]
+    out = np.zeros((nt, nt), dtype=np.uint8, order="F")
+    um = None
+    if user_map is not None:
+        um = np.asfortranarray(user_map, dtype=np.uint8)
+        assert um.shape == (nt, nt)
+    _chk(lib().mpchol_precision_map(h, int(rule), float(eps), None if um is None else um.ctypes.data_as(C.c_void_p),
+                                    out.ctypes.data_as(C.c_void_p)), "mpchol_precision_map")
+    return out
+
+
+def mpchol_factor(h):
+    """Returns info (0, or the 1-based failing column)."""
+    info = C.c_int64(0)
+    _chk(lib().mpchol_factor(h, C.byref(info)), "mpchol_factor", allow_not_spd=True)
+    return int(info.value)
+
+
+def mpchol_logdet(h):
+    v = C.c_double(0.0)
+    _chk(lib().mpchol_logdet(h, C.byref(v)), "mpchol_logdet")
+    return v.value
+
+
+def mpchol_solve(h, B, n):
+    """B: torch float64 column-major (n x nrhs) view or 1-D (n,) tensor on the device; overwritten."""
+    nrhs = 1 if B.dim() == 1 else B.shape[1]
+    _chk(lib().mpchol_solve(h, int(nrhs), _ptr(B), _colmajor_ld(B, n)), "mpchol_solve")
+
+
+def mpchol_sample(h, ndraws, seed, Y, n):
+    _chk(lib().mpchol_sample(h, int(ndraws), C.c_uint64(seed), _ptr(Y), _colmajor_ld(Y, n)), "mpchol_sample")
+
+
+def mpchol_sample_z(h, Z, Y, n):
+    nd = 1 if Z.dim() == 1 else Z.shape[1]
+    _chk(lib().mpchol_sample_z(h, int(nd), _ptr(Z), _colmajor_ld(Z, n), _ptr(Y), _colmajor_ld(Y, n)),
+         "mpchol_sample_z")
+
+
+def mpchol_normal_draws(h, count, seed, z=None, raw=None):
+    _chk(lib().mpchol_normal_draws(h, int(count), C.c_uint64(seed), _ptr(z), _ptr(raw)), "mpchol_normal_draws")
+
+
+def mpchol_backward_error(h, tiles=False, nt=None):
+    be = C.c_double(0.0)
+    tr = None
+    if tiles:
+        nt = nt if nt is not None else mpchol_get_stats(h)["nt"]
+        tr = np.zeros((nt, nt), order="F")
+    _chk(lib().mpchol_backward_error(h, C.byref(be), None if tr is None else tr.ctypes.data_as(C.c_void_p)),
+         "mpchol_backward_error")
+    return (be.value, tr) if tiles else be.value
+
+
+def mpchol_get_factor(h, L, n):
+    _chk(lib().mpchol_get_factor(h, _ptr(L), _colmajor_ld(L, n)), "mpchol_get_factor")
+
+
+def mpchol_get_tile_scales(h, nt):
+    t = np.zeros((nt, nt), dtype=np.int32, order="F")
+    _chk(lib().mpchol_get_tile_scales(h, t.ctypes.data_as(C.c_void_p)), "mpchol_get_tile_scales")
+    return t
+
+
+def mpchol_get_stats(h):
+    s = Stats()
+    _chk(lib().mpchol_get_stats(h, C.byref(s)), "mpchol_get_stats")
+    out = {}
+    for name, _ in Stats._fields_:
+        v = getattr(s, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
+
+
+# --------------------------------------------------------------------- selector
+def mpchol_selector_set(h, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _chk(lib().mpchol_selector_set(h, p.ctypes.data_as(C.c_void_p), p.size), "mpchol_selector_set")
+
+
+def mpchol_selector_features(h, eps, nt):
+    f = np.zeros((nt * nt, 8), dtype=np.float32)
+    _chk(lib().mpchol_selector_features(h, float(eps), f.ctypes.data_as(C.c_void_p)), "mpchol_selector_features")
+    return f
+
+
+def mpchol_selector_labels(h, eps, nt):
+    lab = np.zeros((nt, nt), dtype=np.uint8, order="F")
+    be = C.c_double(0.0)
+    _chk(lib().mpchol_selector_labels(h, float(eps), lab.ctypes.data_as(C.c_void_p), C.byref(be)),
+         "mpchol_selector_labels")
+    return lab, be.value
+
+
+def mpchol_mlp_create(device=0, stream=None):
+    m = C.c_void_p()
+    _chk(lib().mpchol_mlp_create(C.byref(m), int(device), _stream_ptr(stream)), "mpchol_mlp_create")
+    return m
+
+
+def mpchol_mlp_destroy(m):
+    _chk(lib().mpchol_mlp_destroy(m), "mpchol_mlp_destroy")
+
+
+def mpchol_mlp_set_params(m, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _chk(lib().mpchol_mlp_set_params(m, p.ctypes.data_as(C.c_void_p), p.size), "mpchol_mlp_set_params")
+
+
+def mpchol_mlp_get_params(m):
+    p = np.zeros(MLP_NPARAM, dtype=np.float32)
+    _chk(lib().mpchol_mlp_get_params(m, p.ctypes.data_as(C.c_void_p), p.size), "mpchol_mlp_get_params")
+    return p
+
+
+def _cw(cw):
+    return (C.c_float * 4)(*[float(v) for v in cw])
+
+
+def mpchol_mlp_grad(m, X, y, cw, alpha, grad):
+    loss = C.c_float(0.0)
+    _chk(lib().mpchol_mlp_grad(m, _ptr(X), _ptr(y), X.shape[0], _cw(cw), float(alpha), _ptr(grad), C.byref(loss)),
+         "mpchol_mlp_grad")
+    return loss.value
+
+
+def mpchol_mlp_train_step(m, X, y, cw, alpha, lr, want_loss=True):
+    loss = C.c_float(0.0)
+    _chk(lib().mpchol_mlp_train_step(m, _ptr(X), _ptr(y), X.shape[0], _cw(cw), float(alpha), float(lr),
+                                     C.byref(loss) if want_loss else None), "mpchol_mlp_train_step")
+    return loss.value if want_loss else None
+
+
+def mpchol_mlp_predict(m, X, logits=None, cls=None):
+    _chk(lib().mpchol_mlp_predict(m, _ptr(X), X.shape[0], _ptr(logits), _ptr(cls)), "mpchol_mlp_predict")
