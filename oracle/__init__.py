@@ -56,6 +56,7 @@ def lib():
         L.orc_cov_entry.restype = d
         L.orc_cov_entry.argtypes = [dp, dp, d, d, i64, i64]
         L.orc_cov_dense.argtypes = [i64, dp, dp, d, d, dp, i64]
+        L.orc_threads.restype = i32
         L.orc_potrf.restype = i64
         L.orc_potrf.argtypes = [i64, dp, i64]
         L.orc_logdet.restype = d
@@ -82,7 +83,7 @@ def lib():
         L.orc_tile_norms.argtypes = [i64, i64, dp, i64, dp, dp]
         L.orc_map_norm.argtypes = [i64, dp, d, d, i32, C.c_uint, i32, C.POINTER(C.c_uint8)]
         L.orc_mp_factor.restype = i64
-        L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32)]
+        L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_normal_draws.argtypes = [C.c_uint64, i64, dp, u32p]
         L.orc_mlp_nparam.restype = i64
@@ -128,6 +129,11 @@ def potrf(A):
     n = L.shape[0]
     info = lib().orc_potrf(n, _dp(L), n)
     return L, int(info)
+
+
+def threads():
+    """OpenMP threads the oracle runs with."""
+    return int(lib().orc_threads())
 
 
 def logdet(L):
@@ -236,10 +242,11 @@ def map_norm(fro2, total, eps, band=1, allowed=0xF, lo16=F16):
     return out
 
 
-def mp_factor(A, b, cmap, lo16=F16):
+def mp_factor(A, b, cmap, lo16=F16, order=0):
     """O2: (Lhat, info, tscale) -- the tile algorithm replayed with explicit rounding.
 
-    cmap is an nt x nt class map (lower part used; 0 FP64, 1 FP32, 2 16-bit, 3 FP8).
+    cmap is an nt x nt class map (lower part used; 0 FP64, 1 FP32, 2 16-bit, 3 FP8);
+    order 0/1 sums the update products in increasing/decreasing order.
     """
     A = _fortran(A)
     n = A.shape[0]
@@ -249,7 +256,7 @@ def mp_factor(A, b, cmap, lo16=F16):
     Lh = np.zeros((n, n), order="F")
     ts = np.zeros((nt, nt), dtype=np.int32, order="F")
     info = lib().orc_mp_factor(n, b, _dp(A), n, cmap.ctypes.data_as(C.POINTER(C.c_uint8)), lo16, _dp(Lh), n,
-                               ts.ctypes.data_as(C.POINTER(C.c_int32)))
+                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order))
     return Lh, int(info), ts
 
 

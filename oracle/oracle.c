@@ -15,6 +15,7 @@
  * Parity status of each group is stated in its header comment.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -82,6 +83,9 @@ int64_t orc_potrf(int64_t n, double *A, int64_t lda)
         for (int64_t i = 0; i < j; ++i) A[i + j * lda] = 0.0;
     return 0;
 }
+
+/* OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* log det(A) = 2 * sum_i log L_ii, summed in index order. */
 double orc_logdet(int64_t n, const double *L, int64_t ldl)
@@ -440,6 +444,9 @@ void orc_map_norm(int64_t nt, const double *fro2, double total_fro, double eps, 
  *       W = round_f32(W - acc);
  *     16-bit/FP8-class GEMM: acc as above on the scaled copies,
  *       W = round_f32(W - acc * 2^-(t_I + t_J)).
+ * order = 0 sums the update products in increasing c, order = 1 in
+ * decreasing c: two valid executions whose difference calibrates how far
+ * another summation order (the GPU's) may move the result.
  * Output: Lhat (n x n, the represented values of the stored factor),
  * tscale[I + J*nt] = stored scale exponent of tile (I,J).  Returns 0 or the
  * 1-based global column of a failing pivot.
@@ -449,7 +456,7 @@ void orc_map_norm(int64_t nt, const double *fro2, double total_fro, double eps, 
 #define IDX(i, j) ((i) + (size_t)(j) * (size_t)np)
 
 int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const uint8_t *map, int lo16,
-                      double *Lhat, int64_t ldl, int32_t *tscale)
+                      double *Lhat, int64_t ldl, int32_t *tscale, int order)
 {
     int64_t nt = (n + b - 1) / b, np = nt * b;
     double *W = malloc(sizeof(double) * (size_t)np * np);
@@ -553,7 +560,8 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                     /* acc_r = sum_c C_I[r,c] C_J[s,c], terms in c order */
                     if (cls == ORC_P64) {
                         for (int64_t r = 0; r < b; ++r) acc64[r] = 0.0;
-                        for (int64_t c = 0; c < b; ++c) {
+                        for (int64_t cc = 0; cc < b; ++cc) {
+                            int64_t c = order ? b - 1 - cc : cc;
                             double bj = CJ[(j0 + s) + (size_t)c * np];
                             const double *ci = CI + i0 + (size_t)c * np;
                             for (int64_t r = 0; r < b; ++r) acc64[r] += ci[r] * bj;
@@ -561,7 +569,8 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                         for (int64_t r = 0; r < b; ++r) W[IDX(i0 + r, j0 + s)] -= acc64[r];
                     } else {
                         for (int64_t r = 0; r < b; ++r) acc32[r] = 0.0f;
-                        for (int64_t c = 0; c < b; ++c) {
+                        for (int64_t cc = 0; cc < b; ++cc) {
+                            int64_t c = order ? b - 1 - cc : cc;
                             float bj = (float)CJ[(j0 + s) + (size_t)c * np];
                             const double *ci = CI + i0 + (size_t)c * np;
                             for (int64_t r = 0; r < b; ++r) acc32[r] += (float)ci[r] * bj;

@@ -1,0 +1,107 @@
+"""Training driver of the learned precision selector.
+
+Labels come from the method itself (mpchol_selector_labels: per-tile
+residuals measured at each class, greedy lowering under the backward-error
+budget, verified by a factorization); features from mpchol_selector_features;
+training runs the library's forward/backward/Adam kernels
+(mpchol_mlp_train_step).  This module only orchestrates those calls and
+stores the weights.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from . import mpchol as M
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_weights.json")
+
+
+def he_uniform_init(seed: int = 3) -> np.ndarray:
+    """He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero biases."""
+    import synth
+
+    u = synth.uniform01(seed, M.MLP_NPARAM) * 2.0 - 1.0
+    p = np.zeros(M.MLP_NPARAM, dtype=np.float64)
+    layers = [(0, 64 * 8, 8), (64 * 8 + 64, 64 * 64, 64), (64 * 8 + 64 + 64 * 64 + 64, 4 * 64, 64)]
+    for off, cnt, fan_in in layers:
+        p[off:off + cnt] = u[off:off + cnt] * np.sqrt(6.0 / fan_in)
+    return p.astype(np.float32)
+
+
+def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, device=0):
+    """(features [m x 8], labels [m]) of the off-band tiles of one synthetic matrix."""
+    import synth
+
+    sigma, x = synth.workload(L, seed)
+    n = L * L
+    nt = (n + tile - 1) // tile
+    h = M.mpchol_create(n, tile, device=device, lo16=lo16, band=band)
+    try:
+        M.mpchol_set_generator(h, sigma, x, rho, nugget)
+        labels, berr = M.mpchol_selector_labels(h, eps, nt)
+        feats = M.mpchol_selector_features(h, eps, nt)
+    finally:
+        M.mpchol_destroy(h)
+    idx = [(I, J) for J in range(nt) for I in range(J + band + 1, nt)]
+    X = np.array([feats[I + J * nt] for I, J in idx], dtype=np.float32).reshape(-1, 8)
+    y = np.array([labels[I, J] for I, J in idx], dtype=np.int32)
+    return X, y, berr
+
+
+def class_weights(y) -> np.ndarray:
+    cnt = np.bincount(y, minlength=4).astype(np.float64)
+    w = np.where(cnt > 0, cnt.sum() / np.maximum(cnt, 1) / 4.0, 0.0)
+    return np.clip(w, 0.25, 8.0)
+
+
+def train(X, y, steps=600, lr=3e-3, alpha=2.0, seed=3, device=0, log_every=0):
+    """Full-batch Adam on the GPU kernels; returns (params, losses)."""
+    import torch
+
+    m = M.mpchol_mlp_create(device)
+    try:
+        M.mpchol_mlp_set_params(m, he_uniform_init(seed))
+        Xt = torch.tensor(np.ascontiguousarray(X, dtype=np.float32), device=f"cuda:{device}")
+        yt = torch.tensor(np.ascontiguousarray(y, dtype=np.int32), device=f"cuda:{device}")
+        cw = class_weights(y)
+        losses = []
+        for s in range(steps):
+            want = log_every and (s % log_every == 0 or s == steps - 1)
+            l = M.mpchol_mlp_train_step(m, Xt, yt, cw, alpha, lr, want_loss=bool(want))
+            if want:
+                losses.append((s, l))
+        params = M.mpchol_mlp_get_params(m)
+    finally:
+        M.mpchol_mlp_destroy(m)
+    return params, losses
+
+
+def predict(params, X, device=0):
+    import torch
+
+    m = M.mpchol_mlp_create(device)
+    try:
+        M.mpchol_mlp_set_params(m, params)
+        Xt = torch.tensor(np.ascontiguousarray(X, dtype=np.float32), device=f"cuda:{device}")
+        cls = torch.zeros(X.shape[0], dtype=torch.int32, device=f"cuda:{device}")
+        M.mpchol_mlp_predict(m, Xt, cls=cls)
+        torch.cuda.synchronize()
+        return cls.cpu().numpy()
+    finally:
+        M.mpchol_mlp_destroy(m)
+
+
+def save(params, path=WEIGHTS, meta=None):
+    with open(path, "w") as f:
+        json.dump({"nparam": int(M.MLP_NPARAM), "params": [float(v) for v in params], "meta": meta or {}}, f)
+
+
+def load(path=WEIGHTS) -> np.ndarray:
+    with open(path) as f:
+        d = json.load(f)
+    p = np.array(d["params"], dtype=np.float32)
+    assert p.size == M.MLP_NPARAM
+    return p

@@ -1,0 +1,86 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol the header declares, the ctypes structures match the C layout, and
+argument validation happens before any device call."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpchol.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mpchol_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2408_04440_amd.mpchol as M
+
+    L = M.lib()
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_layouts_match_header(tmp_path):
+    import paper_2408_04440_amd.mpchol as M
+
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mpchol.h"\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(mpchol_opts), sizeof(mpchol_stats),'
+                    ' offsetof(mpchol_opts, verify_eps), offsetof(mpchol_stats, t_gemm_ms), offsetof(mpchol_stats, fallbacks));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(M.Opts), C.sizeof(M.Stats), M.Opts.verify_eps.offset, M.Stats.t_gemm_ms.offset,
+            M.Stats.fallbacks.offset]
+    assert got == want
+
+
+def test_strerror_and_codes():
+    import paper_2408_04440_amd.mpchol as M
+
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        s = M.strerror(code)
+        assert s and s != "unknown status"
+    assert M.strerror(12345) == "unknown status"
+
+
+def test_argument_validation_without_gpu():
+    import paper_2408_04440_amd.mpchol as M
+
+    L = M.lib()
+    h = C.c_void_p()
+    assert L.mpchol_create(None, 1024, 128, None) == -1
+    assert L.mpchol_create(C.byref(h), 0, 128, None) == -1
+    assert L.mpchol_create(C.byref(h), 1024, 100, None) == -1   # tile not a multiple of 128
+    assert L.mpchol_create(C.byref(h), 1024, 4096, None) == -1
+    assert h.value is None
+    assert L.mpchol_destroy(None) == 0
+    assert L.mpchol_factor(None, None) == -1
+    assert L.mpchol_logdet(None, None) == -1
+    m = C.c_void_p()
+    assert L.mpchol_mlp_create(None, 0, None) == -1
+
+
+def test_product_never_imports_oracle():
+    pkg = os.path.join(ROOT, "paper_2408_04440_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
+                assert "liboracle" not in txt, f
+                assert "orc_" not in txt, f
+
+
+def test_default_opts():
+    import paper_2408_04440_amd.mpchol as M
+
+    o = M.mpchol_default_opts()
+    assert o.band == 1 and o.allowed == 0xF and o.lo16 == M.LO16_F16 and o.verify_eps == 1e-9
