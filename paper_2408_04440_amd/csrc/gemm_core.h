@@ -39,27 +39,31 @@ template <> struct CM<float> {
     __device__ static inline acc_t mfma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 
-template <typename T, int BM, int BN, int BK>
+// WM x WN waves (64 * WM * WN threads); each wave owns (BM/WM) x (BN/WN) of
+// the block as MB x NB MFMA tiles of 16 x 16.
+template <typename T, int BM, int BN, int BK, int WM = 2, int WN = 2>
 struct CMShape {
+    static constexpr int NTH = 64 * WM * WN;
     static constexpr int VEC = 16 / sizeof(T);
     static constexpr int LDM = BM + CM<T>::PAD, LDN = BN + CM<T>::PAD;
-    static constexpr int CA = BK * BM / VEC / 256;  // 16-byte chunks per thread for A
-    static constexpr int CB = BK * BN / VEC / 256;
-    static constexpr int MB = BM / 32, NB = BN / 32;
+    static constexpr int CHA = BK * BM / VEC, CHB = BK * BN / VEC;  // 16-byte chunks of A and B
+    static constexpr int CA = (CHA + NTH - 1) / NTH, CB = (CHB + NTH - 1) / NTH;  // per thread
+    static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;
     static constexpr size_t SMEM = sizeof(T) * (size_t)2 * BK * (LDM + LDN);
-    static_assert(CA >= 1 && CB >= 1, "block too small for 256 threads");
-    static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA K");
+    static_assert((CHA % NTH == 0 || CHA < NTH) && (CHB % NTH == 0 || CHB < NTH), "load split");
+    static_assert(BK % 4 == 0 && MB >= 1 && NB >= 1, "shape");
 };
 
-// acc -= A * B^T over K (K a multiple of BK).  `neg` selects the sign
-// convention: the caller passes acc to be updated as acc + sgn * A B^T.
-template <typename T, int BM, int BN, int BK>
+// acc += A * B^T over K (K a multiple of BK).
+template <typename T, int BM, int BN, int BK, int WM = 2, int WN = 2>
 __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb, int K,
-                                typename CM<T>::acc_t (&acc)[BM / 32][BN / 32], T *smem)
+                                typename CM<T>::acc_t (&acc)[CMShape<T, BM, BN, BK, WM, WN>::MB]
+                                                              [CMShape<T, BM, BN, BK, WM, WN>::NB],
+                                T *smem)
 {
-    typedef CMShape<T, BM, BN, BK> S;
+    typedef CMShape<T, BM, BN, BK, WM, WN> S;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WM, wn = wave / WM;
     const int gi = lane & 15, gg = lane >> 4;
     T *As = smem;                       // [2][BK][LDM]
     T *Bs = smem + 2 * BK * S::LDM;     // [2][BK][LDN]
@@ -69,29 +73,29 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
     auto gload = [&](int kt) {
 #pragma unroll
         for (int c = 0; c < S::CA; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
-            ra[c] = *(const u32x4 *)(A + r + (int64_t)(kt * BK + col) * lda);
+            if (ch < S::CHA) ra[c] = *(const u32x4 *)(A + r + (int64_t)(kt * BK + col) * lda);
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
-            rb[c] = *(const u32x4 *)(B + r + (int64_t)(kt * BK + col) * ldb);
+            if (ch < S::CHB) rb[c] = *(const u32x4 *)(B + r + (int64_t)(kt * BK + col) * ldb);
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < S::CA; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
-            *(u32x4 *)(As + (buf * BK + col) * S::LDM + r) = ra[c];
+            if (ch < S::CHA) *(u32x4 *)(As + (buf * BK + col) * S::LDM + r) = ra[c];
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
-            *(u32x4 *)(Bs + (buf * BK + col) * S::LDN + r) = rb[c];
+            if (ch < S::CHB) *(u32x4 *)(Bs + (buf * BK + col) * S::LDN + r) = rb[c];
         }
     };
 
@@ -101,8 +105,8 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) gload(kt + 1);
-        const T *as = As + cur * BK * S::LDM + wm * (BM / 2) + gi;
-        const T *bs = Bs + cur * BK * S::LDN + wn * (BN / 2) + gi;
+        const T *as = As + cur * BK * S::LDM + wm * (BM / WM) + gi;
+        const T *bs = Bs + cur * BK * S::LDN + wn * (BN / WN) + gi;
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
             T fa[S::MB], fb[S::NB];
@@ -149,29 +153,32 @@ template <> struct RM<RM_FP8> {
     }
 };
 
-template <int KIND, int BM, int BN, int BK>
+template <int KIND, int BM, int BN, int BK, int WM = 2, int WN = 2>
 struct RMShape {
     typedef typename RM<KIND>::T T;
+    static constexpr int NTH = 64 * WM * WN;
     static constexpr int ROWB = BK * (int)sizeof(T);       // bytes per staged row
     static constexpr int LDB = ROWB + 16;                   // padded row stride in bytes
     static constexpr int CPR = ROWB / 16;                   // 16-byte chunks per row
-    static constexpr int CA = BM * CPR / 256, CB = BN * CPR / 256;
-    static constexpr int MB = BM / 32, NB = BN / 32;
+    static constexpr int CHA = BM * CPR, CHB = BN * CPR;
+    static constexpr int CA = (CHA + NTH - 1) / NTH, CB = (CHB + NTH - 1) / NTH;
+    static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;
     static constexpr size_t SMEM = (size_t)2 * (BM + BN) * LDB;
-    static_assert(CA >= 1 && CB >= 1, "block too small for 256 threads");
-    static_assert(BK % 32 == 0, "BK must be a multiple of the MFMA K");
+    static_assert((CHA % NTH == 0 || CHA < NTH) && (CHB % NTH == 0 || CHB < NTH), "load split");
+    static_assert(BK % 32 == 0 && MB >= 1 && NB >= 1, "shape");
 };
 
-template <int KIND, int BM, int BN, int BK>
+template <int KIND, int BM, int BN, int BK, int WM = 2, int WN = 2>
 __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int64_t lda,
                                 const typename RM<KIND>::T *__restrict__ B, int64_t ldb, int K,
-                                float4_t (&acc)[BM / 32][BN / 32], uint8_t *smem)
+                                float4_t (&acc)[RMShape<KIND, BM, BN, BK, WM, WN>::MB][RMShape<KIND, BM, BN, BK, WM, WN>::NB],
+                                uint8_t *smem)
 {
-    typedef RMShape<KIND, BM, BN, BK> S;
+    typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
     typedef typename RM<KIND>::T T;
     typedef typename RM<KIND>::frag_t F;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WM, wn = wave / WM;
     const int gi = lane & 15, gg = lane >> 4;
     uint8_t *As = smem;                         // [2][BM][LDB]
     uint8_t *Bs = smem + 2 * BM * S::LDB;       // [2][BN][LDB]
@@ -181,29 +188,29 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
     auto gload = [&](int kt) {
 #pragma unroll
         for (int c = 0; c < S::CA; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            ra[c] = *(const u32x4 *)((const uint8_t *)(A + (int64_t)row * lda + kt * BK) + cb);
+            if (ch < S::CHA) ra[c] = *(const u32x4 *)((const uint8_t *)(A + (int64_t)row * lda + kt * BK) + cb);
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            rb[c] = *(const u32x4 *)((const uint8_t *)(B + (int64_t)row * ldb + kt * BK) + cb);
+            if (ch < S::CHB) rb[c] = *(const u32x4 *)((const uint8_t *)(B + (int64_t)row * ldb + kt * BK) + cb);
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int c = 0; c < S::CA; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            *(u32x4 *)(As + (buf * BM + row) * S::LDB + cb) = ra[c];
+            if (ch < S::CHA) *(u32x4 *)(As + (buf * BM + row) * S::LDB + cb) = ra[c];
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
-            int ch = tid + 256 * c;
+            int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            *(u32x4 *)(Bs + (buf * BN + row) * S::LDB + cb) = rb[c];
+            if (ch < S::CHB) *(u32x4 *)(Bs + (buf * BN + row) * S::LDB + cb) = rb[c];
         }
     };
 
@@ -213,8 +220,8 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) gload(kt + 1);
-        const uint8_t *as = As + (cur * BM + wm * (BM / 2) + gi) * S::LDB;
-        const uint8_t *bs = Bs + (cur * BN + wn * (BN / 2) + gi) * S::LDB;
+        const uint8_t *as = As + (cur * BM + wm * (BM / WM) + gi) * S::LDB;
+        const uint8_t *bs = Bs + (cur * BN + wn * (BN / WN) + gi) * S::LDB;
 #pragma unroll
         for (int s = 0; s < BK / 32; ++s) {
             const int kb = (s * 32 + 8 * gg) * (int)sizeof(T);

@@ -8,61 +8,60 @@
 namespace mpc {
 
 // ---------------------------------------------------------------- POTRF
-// Unblocked right-looking Cholesky of the NB x NB block at (j0, j0) of an FP64
-// tile (column-major, leading dimension b), held in LDS.  A pivot that is not
+// Right-looking Cholesky of the 64 x 64 block at (j0, j0) of an FP64 tile
+// (column-major, leading dimension b) by one wavefront, the block held in LDS
+// with lane r owning row r: per column, the pivot and the scaled column are
+// read as broadcasts and each lane updates its own row.  A pivot that is not
 // positive (or NaN) records its 1-based global column in *info (minimum over
-// failures); the computation then continues on NaNs and every kernel still
-// terminates.
-template <int NB>
-__global__ __launch_bounds__(256) void potrf_block_kernel(double *tile, int b, int j0, int64_t col0, int64_t n,
-                                                          unsigned long long *info)
+// failures); the computation then continues on NaNs and still terminates.
+__global__ __launch_bounds__(64) void potrf_block_kernel(double *tile, int b, int j0, int64_t col0, int64_t n,
+                                                         unsigned long long *info)
 {
-    __shared__ double a[NB][NB + 1];  // a[c][r] = tile(j0 + r, j0 + c)
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += 256) {
-        int r = e % NB, c = e / NB;
-        a[c][r] = tile[(j0 + r) + (int64_t)(j0 + c) * b];
-    }
-    for (int c = 0; c < NB; ++c) {
-        __syncthreads();
-        if (tid == 0) {
-            double d = a[c][c];
-            if (!(d > 0.0)) {
-                int64_t col = col0 + j0 + c;
-                if (col < n) atomicMin(info, (unsigned long long)(col + 1));
-            }
-            a[c][c] = sqrt(d);
-        }
-        __syncthreads();
-        const double piv = a[c][c];
-        for (int r = c + 1 + tid; r < NB; r += 256) a[c][r] /= piv;
-        __syncthreads();
-        const int m = NB - c - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            int r = c + 1 + e % m, cc = c + 1 + e / m;
-            if (r >= cc) a[cc][r] -= a[c][r] * a[c][cc];
-        }
-    }
+    __shared__ double a[64][65];  // a[c][r] = A(j0 + r, j0 + c)
+    const int r = threadIdx.x;
+    double *base = tile + j0 + (int64_t)j0 * b;
+    for (int j = 0; j < 64; ++j) a[j][r] = base[r + (int64_t)j * b];
     __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-        int r = e % NB, c = e / NB;
-        tile[(j0 + r) + (int64_t)(j0 + c) * b] = (r >= c) ? a[c][r] : 0.0;
+    for (int c = 0; c < 64; ++c) {
+        const double d = a[c][c];
+        if (r == 0 && !(d > 0.0) && col0 + j0 + c < n) atomicMin(info, (unsigned long long)(col0 + j0 + c + 1));
+        const double piv = sqrt(d);
+        const double l = (r == c) ? piv : a[c][r] / piv;
+        __syncthreads();
+        if (r >= c) a[c][r] = l;
+        __syncthreads();
+        int j = c + 1;
+        for (; j + 3 < 64; j += 4) {
+            const double l0 = a[c][j], l1 = a[c][j + 1], l2 = a[c][j + 2], l3 = a[c][j + 3];
+            if (r >= j) a[j][r] -= l * l0;
+            if (r >= j + 1) a[j + 1][r] -= l * l1;
+            if (r >= j + 2) a[j + 2][r] -= l * l2;
+            if (r >= j + 3) a[j + 3][r] -= l * l3;
+        }
+        for (; j < 64; ++j)
+            if (r >= j) a[j][r] -= l * a[c][j];
+        __syncthreads();
     }
+    for (int j = 0; j < 64; ++j) base[r + (int64_t)j * b] = (r >= j) ? a[j][r] : 0.0;
 }
 
 // ---------------------------------------------------------------- TRSM
 // X = W L^-T for strips of 64 rows (X L^T = W, L lower nL x nL, FP64).
 // Column blocks of 32: the block's right-hand side W - X_left L_row^T is
-// formed with FP64 MFMA from the already solved columns, then solved by
-// substitution against the 32 x 32 diagonal block in LDS.
+// formed with FP64 MFMA from the already solved columns (operands staged
+// through LDS 32 columns at a time), then solved by forward substitution
+// against the 32 x 32 diagonal block, one row per lane in registers.
 // mode 0: the panel of step k -- item I = k+1+blockIdx.y, W = tile (I,k) in
 //         its work precision (FP64, or FP32 for lower classes), X = p64[I];
 // mode 1: one FP64 strip set in place (W = X = xin, leading dimension ldin).
+constexpr int TPAD = 4;
 __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, const double *L, int64_t ldl, int nL,
                                                    double *xin, int64_t ldin, int mode)
 {
-    __shared__ double ts[32][65];  // ts[c][r]
-    __shared__ double lb[32][33];  // lb[c][r] = L(cb + r, cb + c)
+    __shared__ double xs[32][64 + TPAD];  // X chunk: xs[k][row]
+    __shared__ double ls[32][32 + TPAD];  // L chunk: ls[k][c] = L(cb + c, k0 + k)
+    __shared__ double ts[32][64 + 1];     // right-hand side / solution: ts[c][row]
+    __shared__ double lb[32][33];         // diagonal block: lb[c][r] = L(cb + r, cb + c)
     const void *W;
     bool wf32 = false;
     int64_t ldw, ldx;
@@ -83,45 +82,73 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
     const int row0 = blockIdx.x * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gi = lane & 15, gg = lane >> 4;
+    double *Xs = X + row0;
 
     for (int cb = 0; cb < nL; cb += 32) {
-        double4_t acc[2];
-        acc[0] = (double4_t){0.0, 0.0, 0.0, 0.0};
-        acc[1] = acc[0];
-        const double *xa = X + (row0 + wave * 16 + gi);
-        const double *lr0 = L + (cb + gi);
-        for (int kk = 0; kk < cb; kk += 4) {
-            double av = xa[(int64_t)(kk + gg) * ldx];
-            double b0 = lr0[(int64_t)(kk + gg) * ldl];
-            double b1 = lr0[16 + (int64_t)(kk + gg) * ldl];
-            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[1], 0, 0, 0);
+        double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < cb; k0 += 32) {
+            // stage X(rows, k0..k0+31) and L(cb..cb+31, k0..k0+31)
+            {
+                int e = tid;  // 4 x 16-byte chunks of X per thread: 32 cols x 32 chunks
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int ch = e + 256 * q, kk = ch >> 5, r = (ch & 31) * 2;
+                    const double *src = Xs + r + (int64_t)(k0 + kk) * ldx;
+                    xs[kk][r] = src[0];
+                    xs[kk][r + 1] = src[1];
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    int ch = e + 256 * q, kk = ch >> 4, c = (ch & 15) * 2;
+                    const double *src = L + (cb + c) + (int64_t)(k0 + kk) * ldl;
+                    ls[kk][c] = src[0];
+                    ls[kk][c + 1] = src[1];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                double av = xs[s * 4 + gg][wave * 16 + gi];
+                double b0 = ls[s * 4 + gg][gi];
+                double b1 = ls[s * 4 + gg][16 + gi];
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc1, 0, 0, 0);
+            }
+            __syncthreads();
         }
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int r = wave * 16 + acc_row<double>(gg, v), c = nb * 16 + gi;
-                int64_t off = (int64_t)(row0 + r) + (int64_t)(cb + c) * ldw;
-                double w = wf32 ? (double)((const float *)W)[off] : ((const double *)W)[off];
-                ts[c][r] = w - acc[nb][v];
-            }
+        for (int v = 0; v < 4; ++v) {
+            int r = wave * 16 + acc_row<double>(gg, v);
+            int64_t o0 = (int64_t)(row0 + r) + (int64_t)(cb + gi) * ldw;
+            int64_t o1 = o0 + 16 * ldw;
+            double w0 = wf32 ? (double)((const float *)W)[o0] : ((const double *)W)[o0];
+            double w1 = wf32 ? (double)((const float *)W)[o1] : ((const double *)W)[o1];
+            ts[gi][r] = w0 - acc0[v];
+            ts[16 + gi][r] = w1 - acc1[v];
+        }
         for (int e = tid; e < 32 * 32; e += 256) {
             int r = e & 31, c = e >> 5;
             lb[c][r] = L[(cb + r) + (int64_t)(cb + c) * ldl];
         }
         __syncthreads();
-        if (tid < 64) {
+        if (wave == 0) {
+            double t[32];
+#pragma unroll
+            for (int c = 0; c < 32; ++c) t[c] = ts[c][lane];
+#pragma unroll
             for (int c = 0; c < 32; ++c) {
-                double xv = ts[c][tid];
-                for (int cc = 0; cc < c; ++cc) xv -= ts[cc][tid] * lb[cc][c];
-                ts[c][tid] = xv / lb[c][c];
+                double xv = t[c];
+#pragma unroll
+                for (int cc = 0; cc < c; ++cc) xv -= t[cc] * lb[cc][c];
+                t[c] = xv / lb[c][c];
             }
+#pragma unroll
+            for (int c = 0; c < 32; ++c) ts[c][lane] = t[c];
         }
         __syncthreads();
         for (int e = tid; e < 64 * 32; e += 256) {
             int r = e & 63, c = e >> 6;
-            X[(int64_t)(row0 + r) + (int64_t)(cb + c) * ldx] = ts[c][r];
+            Xs[r + (int64_t)(cb + c) * ldx] = ts[c][r];
         }
         __syncthreads();
     }
@@ -159,7 +186,7 @@ void launch_potrf_tile(const Tiles &T, int k, unsigned long long *info, hipStrea
     double *tile = (double *)(T.slots + tile_index(k, k) * T.slot_bytes);
     Panel none{};
     for (int j0 = 0; j0 < b; j0 += 64) {
-        potrf_block_kernel<64><<<1, 256, 0, st>>>(tile, b, j0, (int64_t)k * b, T.n, info);
+        potrf_block_kernel<<<1, 64, 0, st>>>(tile, b, j0, (int64_t)k * b, T.n, info);
         const int M = b - j0 - 64;
         if (M <= 0) break;
         double *xin = tile + (j0 + 64) + (int64_t)j0 * b;
@@ -184,9 +211,10 @@ void launch_trsm_panel(const Tiles &T, const Panel &P, int k, hipStream_t st)
 // update A_IJ -= L_Ik L_Jk^T from the class's panel copies.  Blocks are
 // renumbered XCD-aware so the blocks of one item share an L2; an item with
 // I == J (SYRK, always FP64) computes its lower blocks only.
-template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void update_cm_kernel(Tiles Tt, const T *panel, const int32_t *items)
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const T *panel, const int32_t *items)
 {
+    typedef CMShape<T, BM, BN, BK, WM, WN> S;
     extern __shared__ __align__(16) char smem_raw[];
     const int b = Tt.b;
     const int tmn = b / BM, tnn = b / BN;
@@ -198,32 +226,34 @@ __global__ __launch_bounds__(256) void update_cm_kernel(Tiles Tt, const T *panel
     const int I = it >> 16, J = it & 0xFFFF;
     if (I == J && tn * BN > tm * BM + BM - 1) return;
     const int64_t bb = (int64_t)b * b;
-    typename CM<T>::acc_t acc[BM / 32][BN / 32];
+    typename CM<T>::acc_t acc[S::MB][S::NB];
 #pragma unroll
-    for (int m = 0; m < BM / 32; ++m)
+    for (int m = 0; m < S::MB; ++m)
 #pragma unroll
-        for (int n = 0; n < BN / 32; ++n)
+        for (int n = 0; n < S::NB; ++n)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[m][n][v] = 0;
-    cm_block<T, BM, BN, BK>(panel + I * bb + tm * BM, b, panel + J * bb + tn * BN, b, b, acc, (T *)smem_raw);
+    cm_block<T, BM, BN, BK, WM, WN>(panel + I * bb + tm * BM, b, panel + J * bb + tn * BN, b, b, acc,
+                                    (T *)smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave & 1, wn = wave >> 1, gi = lane & 15, gg = lane >> 4;
+    const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
     T *C = (T *)(Tt.slots + tile_index(I, J) * Tt.slot_bytes) + tm * BM + (int64_t)tn * BN * b;
 #pragma unroll
-    for (int m = 0; m < BM / 32; ++m)
+    for (int m = 0; m < S::MB; ++m)
 #pragma unroll
-        for (int n = 0; n < BN / 32; ++n) {
-            int r = wm * (BM / 2) + m * 16, c = wn * (BN / 2) + n * 16 + gi;
+        for (int n = 0; n < S::NB; ++n) {
+            int r = wm * (BM / WM) + m * 16, c = wn * (BN / WN) + n * 16 + gi;
             T *p = C + r + (int64_t)c * b;
 #pragma unroll
             for (int v = 0; v < 4; ++v) p[acc_row<T>(gg, v)] -= acc[m][n][v];
         }
 }
 
-template <int KIND, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void update_rm_kernel(Tiles Tt, const typename RM<KIND>::T *panel,
-                                                        const int32_t *pscale, int q, const int32_t *items)
+template <int KIND, int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const typename RM<KIND>::T *panel,
+                                                                 const int32_t *pscale, int q, const int32_t *items)
 {
+    typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
     extern __shared__ __align__(16) char smem_raw[];
     const int b = Tt.b;
     const int tmn = b / BM, tnn = b / BN;
@@ -234,58 +264,82 @@ __global__ __launch_bounds__(256) void update_rm_kernel(Tiles Tt, const typename
     const int32_t it = items[item];
     const int I = it >> 16, J = it & 0xFFFF;
     const int64_t bb = (int64_t)b * b;
-    float4_t acc[BM / 32][BN / 32];
+    float4_t acc[S::MB][S::NB];
 #pragma unroll
-    for (int m = 0; m < BM / 32; ++m)
+    for (int m = 0; m < S::MB; ++m)
 #pragma unroll
-        for (int n = 0; n < BN / 32; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    rm_block<KIND, BM, BN, BK>(panel + I * bb + (int64_t)tm * BM * b, b, panel + J * bb + (int64_t)tn * BN * b, b, b,
-                               acc, (uint8_t *)smem_raw);
+        for (int n = 0; n < S::NB; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    rm_block<KIND, BM, BN, BK, WM, WN>(panel + I * bb + (int64_t)tm * BM * b, b, panel + J * bb + (int64_t)tn * BN * b,
+                                       b, b, acc, (uint8_t *)smem_raw);
     const int tsum = pscale[I * 4 + q] + pscale[J * 4 + q];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave & 1, wn = wave >> 1, gi = lane & 15, gg = lane >> 4;
+    const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
     float *C = (float *)(Tt.slots + tile_index(I, J) * Tt.slot_bytes) + tm * BM + (int64_t)tn * BN * b;
 #pragma unroll
-    for (int m = 0; m < BM / 32; ++m)
+    for (int m = 0; m < S::MB; ++m)
 #pragma unroll
-        for (int n = 0; n < BN / 32; ++n) {
-            int r = wm * (BM / 2) + m * 16 + 4 * gg, c = wn * (BN / 2) + n * 16 + gi;
+        for (int n = 0; n < S::NB; ++n) {
+            int r = wm * (BM / WM) + m * 16 + 4 * gg, c = wn * (BN / WN) + n * 16 + gi;
             float *p = C + r + (int64_t)c * b;
 #pragma unroll
             for (int v = 0; v < 4; ++v) p[v] -= ldexpf(acc[m][n][v], -tsum);
         }
 }
 
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+static void launch_cm(const Tiles &T_, const T *panel, const int32_t *items, int nitems, hipStream_t st)
+{
+    typedef CMShape<T, BM, BN, BK, WM, WN> S;
+    auto k = update_cm_kernel<T, BM, BN, BK, WM, WN>;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::SMEM);
+        attr = true;
+    }
+    const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel, items);
+}
+
+template <int KIND, int BM, int BN, int BK, int WM, int WN>
+static void launch_rm(const Tiles &T_, const typename RM<KIND>::T *panel, const int32_t *pscale, int q,
+                      const int32_t *items, int nitems, hipStream_t st)
+{
+    typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
+    auto k = update_rm_kernel<KIND, BM, BN, BK, WM, WN>;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::SMEM);
+        attr = true;
+    }
+    const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel, pscale, q, items);
+}
+
+// Block shapes per class from a sweep on MI355X (1024 x 1024 tiles):
+// FP64 128 x 128 with 16 waves of 32 x 32, FP32 256 x 128 with 8 waves,
+// FP16/BF16 256 x 256 with 16 waves, FP8 128 x 128 with 4 waves; tiles of
+// 128 fall back to 128 x 128 blocks.
 void launch_update(const Tiles &T, const Panel &P, int q, const int32_t *items, int nitems, hipStream_t st)
 {
     if (nitems <= 0) return;
-    const int b = T.b;
-    const int64_t bb = (int64_t)b * b;
-    constexpr int BM = 128, BN = 128;
-    const int64_t grid = (int64_t)nitems * (b / BM) * (b / BN);
+    const bool big = (T.b % 256) == 0;
     switch (q) {
-    case P64:
-        update_cm_kernel<double, BM, BN, 16><<<(unsigned)grid, 256, CMShape<double, BM, BN, 16>::SMEM, st>>>(
-            T, P.p64, items);
-        break;
+    case P64: launch_cm<double, 128, 128, 16, 4, 4>(T, P.p64, items, nitems, st); break;
     case P32:
-        update_cm_kernel<float, BM, BN, 16><<<(unsigned)grid, 256, CMShape<float, BM, BN, 16>::SMEM, st>>>(
-            T, P.p32, items);
+        if (big) launch_cm<float, 256, 128, 16, 4, 2>(T, P.p32, items, nitems, st);
+        else launch_cm<float, 128, 128, 16, 2, 2>(T, P.p32, items, nitems, st);
         break;
     case P16:
-        if (T.lo16 == LO16_BF16)
-            update_rm_kernel<RM_BF16, BM, BN, 64><<<(unsigned)grid, 256, RMShape<RM_BF16, BM, BN, 64>::SMEM, st>>>(
-                T, P.p16, P.pscale, q, items);
-        else
-            update_rm_kernel<RM_F16, BM, BN, 64><<<(unsigned)grid, 256, RMShape<RM_F16, BM, BN, 64>::SMEM, st>>>(
-                T, P.p16, P.pscale, q, items);
+        if (T.lo16 == LO16_BF16) {
+            if (big) launch_rm<RM_BF16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, q, items, nitems, st);
+            else launch_rm<RM_BF16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, q, items, nitems, st);
+        } else {
+            if (big) launch_rm<RM_F16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, q, items, nitems, st);
+            else launch_rm<RM_F16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, q, items, nitems, st);
+        }
         break;
-    default:
-        update_rm_kernel<RM_FP8, BM, BN, 128><<<(unsigned)grid, 256, RMShape<RM_FP8, BM, BN, 128>::SMEM, st>>>(
-            T, P.p8, P.pscale, q, items);
-        break;
+    default: launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, P.p8, P.pscale, q, items, nitems, st); break;
     }
-    (void)bb;
 }
 
 }  // namespace mpc

@@ -45,7 +45,9 @@ struct mpchol_handle {
     double *d_sigma = nullptr, *d_x = nullptr;
     double rho = 0, nugget = 0;
     int src = 0;  // 0 none, 1 matrix, 2 generator
-    // panel copies
+    hipStream_t st2 = nullptr;           // look-ahead stream for the panel of the next step
+    hipEvent_t ev_next = nullptr, ev_panel = nullptr;
+    // panel copies, two sets (even / odd steps)
     double *p64 = nullptr;
     float *p32 = nullptr;
     uint16_t *p16 = nullptr;
@@ -64,7 +66,7 @@ struct mpchol_handle {
     double last_eps = 1e-9;
     // schedule
     int32_t *d_items = nullptr;
-    std::vector<int64_t> item_off;  // (nt * 4 + 1) offsets, step-major, class-minor
+    std::vector<int64_t> item_off;  // (nt * 8 + 1) offsets: step, class, part (0: column k+1, 1: the rest)
     uint8_t *d_qmask = nullptr;
     int32_t *d_all_items = nullptr;  // every lower tile, for the residual
     double *d_partial = nullptr, *d_tres2 = nullptr;
@@ -102,15 +104,16 @@ struct mpchol_handle {
         S.orig = orig;
         return S;
     }
-    Panel panel() const
+    Panel panel(int set) const
     {
+        const size_t bb = (size_t)b * b;
         Panel P;
-        P.p64 = p64;
-        P.p32 = p32;
-        P.p16 = p16;
-        P.p8 = p8;
-        P.pmax = pmax;
-        P.pscale = pscale;
+        P.p64 = p64 + set * nt * bb;
+        P.p32 = p32 + set * nt * bb;
+        P.p16 = p16 + set * nt * bb;
+        P.p8 = p8 + set * nt * bb;
+        P.pmax = pmax + set * nt;
+        P.pscale = pscale + set * nt * 4;
         return P;
     }
 };
@@ -143,6 +146,9 @@ static void release(mpchol_handle *h)
     for (auto &e : h->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto e : h->gev) (void)hipEventDestroy(e);
+    if (h->ev_next) (void)hipEventDestroy(h->ev_next);
+    if (h->ev_panel) (void)hipEventDestroy(h->ev_panel);
+    if (h->st2) (void)hipStreamDestroy(h->st2);
 }
 
 extern "C" {
@@ -212,12 +218,12 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
         if (rc == MPCHOL_OK && r != MPCHOL_OK) rc = r;
     };
     A(dalloc(&h->slots, h->ntile * h->slot_bytes));
-    A(dalloc(&h->p64, nt * bb * 8));
-    A(dalloc(&h->p32, nt * bb * 4));
-    A(dalloc(&h->p16, nt * bb * 2));
-    A(dalloc(&h->p8, nt * bb));
-    A(dalloc(&h->pmax, nt * 8));
-    A(dalloc(&h->pscale, nt * 4 * 4));
+    A(dalloc(&h->p64, 2 * nt * bb * 8));
+    A(dalloc(&h->p32, 2 * nt * bb * 4));
+    A(dalloc(&h->p16, 2 * nt * bb * 2));
+    A(dalloc(&h->p8, 2 * nt * bb));
+    A(dalloc(&h->pmax, 2 * nt * 8));
+    A(dalloc(&h->pscale, 2 * nt * 4 * 4));
     A(dalloc(&h->d_map, nt * nt));
     A(dalloc(&h->d_tscale, nt * nt * 4));
     A(dalloc(&h->d_fro2, nt * nt * 8));
@@ -232,6 +238,9 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     A(dalloc(&h->d_feats, nt * nt * 8 * 4));
     for (auto &e : h->ev)
         if (rc == MPCHOL_OK && hipEventCreate(&e) != hipSuccess) rc = MPCHOL_EHIP;
+    if (rc == MPCHOL_OK && hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking) != hipSuccess) rc = MPCHOL_EHIP;
+    if (rc == MPCHOL_OK && hipEventCreateWithFlags(&h->ev_next, hipEventDisableTiming) != hipSuccess) rc = MPCHOL_EHIP;
+    if (rc == MPCHOL_OK && hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess) rc = MPCHOL_EHIP;
     if (rc == MPCHOL_OK) {
         std::vector<int32_t> all;
         all.reserve(h->ntile);
@@ -380,21 +389,27 @@ static void rule_band(mpchol_handle *h, std::vector<uint8_t> &m)
         }
 }
 
+// Static schedule: for every step k and class q, the update items (I, J),
+// k < J <= I, of that class -- first those of column J = k+1 (which the next
+// step's panel needs), then the rest -- and, per panel tile (I, k), the mask
+// of classes its consumers use.
 static void build_schedule_counts(mpchol_handle *h, std::vector<int32_t> &items, std::vector<uint8_t> &qmask)
 {
     const int nt = h->nt;
-    h->item_off.assign((size_t)nt * 4 + 1, 0);
+    h->item_off.assign((size_t)nt * 8 + 1, 0);
     items.clear();
     for (int k = 0; k < nt; ++k)
-        for (int q = 0; q < 4; ++q) {
-            h->item_off[(size_t)k * 4 + q] = (int64_t)items.size();
-            for (int J = k + 1; J < nt; ++J)
-                for (int I = J; I < nt; ++I) {
-                    int c = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
-                    if (c == q) items.push_back((I << 16) | J);
-                }
-        }
-    h->item_off[(size_t)nt * 4] = (int64_t)items.size();
+        for (int q = 0; q < 4; ++q)
+            for (int part = 0; part < 2; ++part) {
+                h->item_off[((size_t)k * 4 + q) * 2 + part] = (int64_t)items.size();
+                const int jlo = part == 0 ? k + 1 : k + 2, jhi = part == 0 ? k + 1 : nt - 1;
+                for (int J = jlo; J <= jhi && J < nt; ++J)
+                    for (int I = J; I < nt; ++I) {
+                        int c = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
+                        if (c == q) items.push_back((I << 16) | J);
+                    }
+            }
+    h->item_off[(size_t)nt * 8] = (int64_t)items.size();
     qmask.assign((size_t)nt * nt, 0);
     for (int k = 0; k < nt; ++k)
         for (int I = k + 1; I < nt; ++I) {
@@ -522,49 +537,84 @@ extern "C" int mpchol_precision_map(mpchol_t h, int32_t rule, double eps, const 
     return MPCHOL_OK;
 }
 
+// Panel work of step k on stream st: TRSM of the tiles below the diagonal
+// into the FP64 panel, max |X| per tile, and the sender-side conversion.
+static int panel_step(mpchol_handle *h, const Tiles &T, const Panel &P, int k, hipStream_t st)
+{
+    launch_trsm_panel(T, P, k, st);
+    HIPCHK(hipMemsetAsync(P.pmax, 0, (size_t)h->nt * 8, st));
+    launch_panel_max(T, P, k, st);
+    launch_convert(T, P, k, h->d_qmask + (size_t)k * h->nt, st);
+    return MPCHOL_OK;
+}
+
+static int update_part(mpchol_handle *h, const Tiles &T, const Panel &P, int k, int part, hipStream_t st)
+{
+    const double b3 = (double)h->b * h->b * h->b;
+    for (int q = 0; q < 4; ++q) {
+        const size_t o = ((size_t)k * 4 + q) * 2 + part;
+        const int64_t off = h->item_off[o];
+        const int cnt = (int)(h->item_off[o + 1] - off);
+        if (cnt <= 0) continue;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->o.profile) {
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            HIPCHK(hipEventRecord(e0, st));
+        }
+        launch_update(T, P, q, h->d_items + off, cnt, st);
+        if (h->o.profile) {
+            HIPCHK(hipEventRecord(e1, st));
+            h->gev.push_back(e0);
+            h->gev.push_back(e1);
+            h->gev_class.push_back(q);
+            h->gev_flops.push_back(2.0 * b3 * cnt);
+        }
+    }
+    return MPCHOL_OK;
+}
+
+// Right-looking tile algorithm with look-ahead of depth one: the caller's
+// stream A runs the trailing updates; once column k+1 is updated, a second
+// stream B factors tile (k+1,k+1), solves and converts panel k+1 (into the
+// other panel set) while A finishes the rest of step k.
 static int run_factor(mpchol_handle *h, int64_t *info)
 {
     const int nt = h->nt;
     Tiles T = h->tiles();
-    Panel P = h->panel();
+    const Panel P[2] = {h->panel(0), h->panel(1)};
+    hipStream_t A = h->st, B = h->st2;
     for (auto e : h->gev) (void)hipEventDestroy(e);
     h->gev.clear();
     h->gev_class.clear();
     h->gev_flops.clear();
-    HIPCHK(hipMemsetAsync(h->d_info, 0xFF, 8, h->st));
-    HIPCHK(hipEventRecord(h->ev[0], h->st));
-    const double b3 = (double)h->b * h->b * h->b;
-    for (int k = 0; k < nt; ++k) {
-        launch_potrf_tile(T, k, h->d_info, h->st);
-        if (k == nt - 1) break;
-        launch_trsm_panel(T, P, k, h->st);
-        HIPCHK(hipMemsetAsync(h->pmax, 0, (size_t)nt * 8, h->st));
-        launch_panel_max(T, P, k, h->st);
-        launch_convert(T, P, k, h->d_qmask + (size_t)k * nt, h->st);
-        for (int q = 0; q < 4; ++q) {
-            int64_t off = h->item_off[(size_t)k * 4 + q];
-            int cnt = (int)(h->item_off[(size_t)k * 4 + q + 1] - off);
-            if (cnt <= 0) continue;
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (h->o.profile) {
-                HIPCHK(hipEventCreate(&e0));
-                HIPCHK(hipEventCreate(&e1));
-                HIPCHK(hipEventRecord(e0, h->st));
-            }
-            launch_update(T, P, q, h->d_items + off, cnt, h->st);
-            if (h->o.profile) {
-                HIPCHK(hipEventRecord(e1, h->st));
-                h->gev.push_back(e0);
-                h->gev.push_back(e1);
-                h->gev_class.push_back(q);
-                h->gev_flops.push_back(2.0 * b3 * cnt);
-            }
-        }
+    HIPCHK(hipMemsetAsync(h->d_info, 0xFF, 8, A));
+    HIPCHK(hipEventRecord(h->ev[0], A));
+    launch_potrf_tile(T, 0, h->d_info, A);
+    if (nt > 1) {
+        int rc = panel_step(h, T, P[0], 0, A);
+        if (rc) return rc;
     }
-    HIPCHK(hipEventRecord(h->ev[1], h->st));
+    for (int k = 0; k + 1 < nt; ++k) {
+        const Panel &Pk = P[k & 1], &Pn = P[(k + 1) & 1];
+        int rc = update_part(h, T, Pk, k, 0, A);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(h->ev_next, A));
+        HIPCHK(hipStreamWaitEvent(B, h->ev_next, 0));
+        launch_potrf_tile(T, k + 1, h->d_info, B);
+        if (k + 2 < nt) {
+            rc = panel_step(h, T, Pn, k + 1, B);
+            if (rc) return rc;
+        }
+        HIPCHK(hipEventRecord(h->ev_panel, B));
+        rc = update_part(h, T, Pk, k, 1, A);
+        if (rc) return rc;
+        HIPCHK(hipStreamWaitEvent(A, h->ev_panel, 0));
+    }
+    HIPCHK(hipEventRecord(h->ev[1], A));
     unsigned long long hinfo = 0;
-    HIPCHK(hipMemcpyAsync(&hinfo, h->d_info, 8, hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipMemcpyAsync(&hinfo, h->d_info, 8, hipMemcpyDeviceToHost, A));
+    HIPCHK(hipStreamSynchronize(A));
     HIPCHK(hipGetLastError());
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
