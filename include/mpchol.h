@@ -101,7 +101,7 @@ typedef struct mpchol_stats {
 void mpchol_default_opts(mpchol_opts *o);
 
 /* Create a handle for an n x n matrix in tiles of tile x tile (tile a multiple
- * of 64, 64..2048).  n need not be a multiple of tile: the last tile row and
+ * of 128, 128..2048).  n need not be a multiple of tile: the last tile row and
  * column are padded with an identity block, which changes neither the factor
  * nor the log-determinant.  Allocates the tile storage (about
  * NT(NT+1)/2 * tile^2 * 8 bytes) and the panel buffers on o->device.
@@ -184,6 +184,11 @@ int mpchol_get_stats(mpchol_t h, mpchol_stats *s);
 
 /* Static description of a status code. */
 const char *mpchol_strerror(int status);
+
+/* Text of the last HIP failure seen by a call on this thread (the failing
+ * runtime call and its error string); empty if none.  Owned by the library,
+ * valid until the next call on this thread. */
+const char *mpchol_last_error(void);
 
 /* ---- learned precision selector -------------------------------------- */
 /* A multilayer perceptron 8 -> 64 -> 64 -> 4 (ReLU, FP32) mapping tile

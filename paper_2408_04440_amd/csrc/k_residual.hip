@@ -17,29 +17,32 @@ __device__ inline double source_at(const Tiles &T, const Source &S, int I, int J
     return v;
 }
 
-constexpr int RB = 128, RK = 16, RLD = RB + 16;
+// 128 x 128 output block per workgroup, 16 waves of 32 x 32 (the FP64
+// update's shape), K staged 16 columns at a time through LDS.
+constexpr int RB = 128, RK = 16, RLD = RB + 16, RW = 4, RNT = 64 * RW * RW, RPER = RK * RB / RNT;
 
-__global__ __launch_bounds__(256) void residual_kernel(Tiles T, Source S, const int32_t *items, double *partial)
+__global__ __launch_bounds__(RNT) void residual_kernel(Tiles T, Source S, const int32_t *items, double *partial)
 {
     __shared__ double As[2][RK][RLD], Bs[2][RK][RLD];
-    __shared__ double red[256];
+    __shared__ double red[RNT];
     const int b = T.b, nsub = b / RB;
     const int item = blockIdx.x / (nsub * nsub), rem = blockIdx.x % (nsub * nsub);
     const int tm = rem % nsub, tn = rem / nsub;
     const int32_t it = items[item];
     const int I = it >> 16, J = it & 0xFFFF;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1, gi = lane & 15, gg = lane >> 4;
-    double4_t acc[4][4];
+    const int wm = wave % RW, wn = wave / RW, gi = lane & 15, gg = lane >> 4;
+    constexpr int WT = RB / RW;  // 32
+    double4_t acc[2][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < 2; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
     const bool skip = (I == J && tn > tm);
     if (!skip) {
         const int nkt = b / RK;
-        double ra[8], rb[8];
+        double ra[RPER], rb[RPER];
         for (int K = 0; K <= J; ++K) {
             const int ca = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
             const int cbc = (J == K) ? P64 : T.map[J + (int64_t)K * T.nt];
@@ -48,8 +51,8 @@ __global__ __launch_bounds__(256) void residual_kernel(Tiles T, Source S, const 
             const char *sb = T.slots + tile_index(J, K) * T.slot_bytes;
             auto gload = [&](int kt) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    int e = tid + 256 * c;  // 0 .. RK*RB-1
+                for (int c = 0; c < RPER; ++c) {
+                    int e = tid + RNT * c;  // 0 .. RK*RB-1
                     int r = e % RB, col = e / RB;
                     int64_t off = (int64_t)(tm * RB + r) + (int64_t)(kt * RK + col) * b;
                     int64_t offb = (int64_t)(tn * RB + r) + (int64_t)(kt * RK + col) * b;
@@ -59,8 +62,8 @@ __global__ __launch_bounds__(256) void residual_kernel(Tiles T, Source S, const 
             };
             auto sstore = [&](int buf) {
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    int e = tid + 256 * c;
+                for (int c = 0; c < RPER; ++c) {
+                    int e = tid + RNT * c;
                     int r = e % RB, col = e / RB;
                     As[buf][col][r] = ra[c];
                     Bs[buf][col][r] = rb[c];
@@ -74,15 +77,15 @@ __global__ __launch_bounds__(256) void residual_kernel(Tiles T, Source S, const 
                 if (kt + 1 < nkt) gload(kt + 1);
 #pragma unroll
                 for (int s = 0; s < RK / 4; ++s) {
-                    double fa[4], fb[4];
+                    double fa[2], fb[2];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) fa[m] = As[cur][s * 4 + gg][wm * 64 + m * 16 + gi];
+                    for (int m = 0; m < 2; ++m) fa[m] = As[cur][s * 4 + gg][wm * WT + m * 16 + gi];
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) fb[n] = Bs[cur][s * 4 + gg][wn * 64 + n * 16 + gi];
+                    for (int n = 0; n < 2; ++n) fb[n] = Bs[cur][s * 4 + gg][wn * WT + n * 16 + gi];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
+                    for (int m = 0; m < 2; ++m)
 #pragma unroll
-                        for (int n = 0; n < 4; ++n)
+                        for (int n = 0; n < 2; ++n)
                             acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[m], fb[n], acc[m][n], 0, 0, 0);
                 }
                 if (kt + 1 < nkt) sstore(cur ^ 1);
@@ -93,12 +96,12 @@ __global__ __launch_bounds__(256) void residual_kernel(Tiles T, Source S, const 
     double s2 = 0.0;
     if (!skip) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n)
+            for (int n = 0; n < 2; ++n)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    int r = tm * RB + wm * 64 + m * 16 + acc_row<double>(gg, v), c = tn * RB + wn * 64 + n * 16 + gi;
+                    int r = tm * RB + wm * WT + m * 16 + acc_row<double>(gg, v), c = tn * RB + wn * WT + n * 16 + gi;
                     int64_t i = (int64_t)I * b + r, j = (int64_t)J * b + c;
                     if (i >= T.n || j >= T.n || i < j) continue;
                     double res = source_at(T, S, I, J, r, c) - acc[m][n][v];
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void residual_kernel(Tiles T, Source S, const 
     }
     red[tid] = s2;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = RNT / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
@@ -131,7 +134,7 @@ void launch_residual_items(const Tiles &T, const Source &S, const int32_t *items
                            double *tile_res2, hipStream_t st)
 {
     const int nsub = T.b / RB;
-    residual_kernel<<<(unsigned)((int64_t)nitems * nsub * nsub), 256, 0, st>>>(T, S, items, partial);
+    residual_kernel<<<(unsigned)((int64_t)nitems * nsub * nsub), RNT, 0, st>>>(T, S, items, partial);
     residual_reduce_kernel<<<(nitems + 255) / 256, 256, 0, st>>>(items, nitems, nsub * nsub, partial, T.nt, tile_res2);
 }
 

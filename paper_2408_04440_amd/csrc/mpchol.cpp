@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -118,9 +119,21 @@ struct mpchol_handle {
     }
 };
 
-#define HIPCHK(x)                                      \
-    do {                                               \
-        if ((x) != hipSuccess) return MPCHOL_EHIP;     \
+// Text of the last failing HIP call on this thread (mpchol_last_error).
+static thread_local char g_last_error[512] = "";
+
+static int hip_fail(hipError_t e, const char *expr, int line)
+{
+    snprintf(g_last_error, sizeof(g_last_error), "%s failed: %s (%d) at mpchol.cpp:%d", expr, hipGetErrorString(e),
+             (int)e, line);
+    (void)hipGetLastError();
+    return MPCHOL_EHIP;
+}
+
+#define HIPCHK(x)                                                   \
+    do {                                                            \
+        hipError_t e_ = (x);                                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__);    \
     } while (0)
 
 template <typename T>
@@ -128,9 +141,10 @@ static int dalloc(T **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) return MPCHOL_OK;
-    if (hipMalloc((void **)p, bytes) != hipSuccess) {
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
         *p = nullptr;
-        (void)hipGetLastError();
+        hip_fail(e, "hipMalloc", __LINE__);
         return MPCHOL_ENOMEM;
     }
     return MPCHOL_OK;
@@ -168,6 +182,8 @@ void mpchol_default_opts(mpchol_opts *o)
     o->profile = 0;
 }
 
+const char *mpchol_last_error(void) { return g_last_error; }
+
 const char *mpchol_strerror(int s)
 {
     switch (s) {
@@ -196,11 +212,12 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     if (opt.lo16 != MPCHOL_LO16_F16 && opt.lo16 != MPCHOL_LO16_BF16) return MPCHOL_EINVAL;
     if (opt.band < 0) return MPCHOL_EINVAL;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || opt.device < 0 || opt.device >= ndev) {
-        (void)hipGetLastError();
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (opt.device < 0 || opt.device >= ndev) {
+        snprintf(g_last_error, sizeof(g_last_error), "device %d not present (%d visible)", opt.device, ndev);
         return MPCHOL_EHIP;
     }
-    if (hipSetDevice(opt.device) != hipSuccess) return MPCHOL_EHIP;
+    HIPCHK(hipSetDevice(opt.device));
 
     mpchol_handle *h = new (std::nothrow) mpchol_handle();
     if (!h) return MPCHOL_ENOMEM;
@@ -236,19 +253,22 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     A(dalloc(&h->d_tres2, nt * nt * 8));
     A(dalloc(&h->d_params, MPCHOL_MLP_NPARAM * 4));
     A(dalloc(&h->d_feats, nt * nt * 8 * 4));
+    auto H = [&](hipError_t e, const char *what) {
+        if (rc == MPCHOL_OK && e != hipSuccess) rc = hip_fail(e, what, __LINE__);
+    };
     for (auto &e : h->ev)
-        if (rc == MPCHOL_OK && hipEventCreate(&e) != hipSuccess) rc = MPCHOL_EHIP;
-    if (rc == MPCHOL_OK && hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking) != hipSuccess) rc = MPCHOL_EHIP;
-    if (rc == MPCHOL_OK && hipEventCreateWithFlags(&h->ev_next, hipEventDisableTiming) != hipSuccess) rc = MPCHOL_EHIP;
-    if (rc == MPCHOL_OK && hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess) rc = MPCHOL_EHIP;
+        if (rc == MPCHOL_OK) H(hipEventCreate(&e), "hipEventCreate");
+    if (rc == MPCHOL_OK) H(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    if (rc == MPCHOL_OK) H(hipEventCreateWithFlags(&h->ev_next, hipEventDisableTiming), "hipEventCreateWithFlags");
+    if (rc == MPCHOL_OK) H(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming), "hipEventCreateWithFlags");
     if (rc == MPCHOL_OK) {
         std::vector<int32_t> all;
         all.reserve(h->ntile);
         for (int I = 0; I < nt; ++I)
             for (int J = 0; J <= I; ++J) all.push_back((I << 16) | J);
-        if (hipMemcpy(h->d_all_items, all.data(), all.size() * 4, hipMemcpyHostToDevice) != hipSuccess) rc = MPCHOL_EHIP;
-        if (hipMemset(h->d_tscale, 0, nt * nt * 4) != hipSuccess) rc = MPCHOL_EHIP;
-        if (hipMemset(h->d_map, 0, nt * nt) != hipSuccess) rc = MPCHOL_EHIP;
+        H(hipMemcpy(h->d_all_items, all.data(), all.size() * 4, hipMemcpyHostToDevice), "hipMemcpy(items)");
+        H(hipMemset(h->d_tscale, 0, nt * nt * 4), "hipMemset(tscale)");
+        H(hipMemset(h->d_map, 0, nt * nt), "hipMemset(map)");
     }
     if (rc != MPCHOL_OK) {
         release(h);

@@ -26,7 +26,8 @@ MLP_NPARAM = 4996
 class MpcholError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
-        super().__init__(f"{where}: {strerror(status)} ({status})")
+        detail = last_error() if status == -3 or status == -2 else ""
+        super().__init__(f"{where}: {strerror(status)} ({status})" + (f" [{detail}]" if detail else ""))
 
 
 class Opts(C.Structure):
@@ -47,9 +48,20 @@ _lib = None
 
 
 def lib():
-    """Load libmpchol.so; raises if it has not been built."""
+    """Load libmpchol.so; raises if it has not been built.
+
+    torch is imported first: its bundled HIP runtime carries the same SONAME
+    (libamdhip64.so.7) as the one libmpchol.so links, so loading torch first
+    makes the library bind to torch's runtime -- one runtime per process,
+    whose streams and device pointers both sides share.  Loading the library
+    first would bring in a second HIP runtime when torch is imported later.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIBPATH):
             raise ImportError(f"libmpchol.so not built at {LIBPATH}: run __graft_entry__.build() "
                               "or python paper_2408_04440_amd/build.py")
@@ -73,6 +85,7 @@ def lib():
             "mpchol_get_tile_scales": (C.c_int, [vp, vp]),
             "mpchol_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
             "mpchol_strerror": (C.c_char_p, [C.c_int]),
+            "mpchol_last_error": (C.c_char_p, []),
             "mpchol_selector_set": (C.c_int, [vp, vp, i64]),
             "mpchol_selector_features": (C.c_int, [vp, d, vp]),
             "mpchol_selector_labels": (C.c_int, [vp, d, vp, C.POINTER(d)]),
@@ -94,6 +107,10 @@ def lib():
 
 def strerror(status: int) -> str:
     return lib().mpchol_strerror(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().mpchol_last_error().decode()
 
 
 def _chk(rc, where, allow_not_spd=False):
