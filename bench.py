@@ -77,6 +77,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-berr", action="store_true", help="skip the FP64 residual check")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
+    ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band"],
+                    help="precision map of the timed steps (default: norm, or fp64 for FP64-only workloads)")
+    ap.add_argument("--compare", default="", help="comma list of extra rules timed once after the steps, "
+                    "each with its backward error (e.g. norm,learned)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="run one plain device copy of MB megabytes first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -90,16 +97,34 @@ def main():
 
     cfg = CONFIGS[args.config]
     L, tile, rho, eps = cfg["L"], cfg["tile"], cfg["rho"], cfg["eps"]
+    if args.rho is not None:
+        rho = args.rho
     n = L * L
     nugget = 1e-8
     flops = n ** 3 / 3.0
     sigma, x = synth.workload(L)
     log(f"bench: config={args.config} N={n} tile={tile} rho={rho} eps={eps} classes={cfg['label']}")
 
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"  copy calibration: {nb} bytes read, {nb} bytes written by one copy kernel")
+        del src, dst
+
+    RULES = {"norm": M.RULE_NORM, "learned": M.RULE_LEARNED, "fp64": M.RULE_FP64, "band": M.RULE_BAND}
     stream = torch.cuda.current_stream()
-    h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1)
+    need_w = args.rule == "learned" or "learned" in args.compare
+    h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
+                        verify=1 if need_w else 0, verify_eps=eps)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
-    rule = M.RULE_NORM if cfg["allowed"] != 1 else M.RULE_FP64
+    if need_w:
+        from paper_2408_04440_amd import selector as S
+
+        M.mpchol_selector_set(h, S.load())
+    rule = RULES[args.rule] if args.rule else (M.RULE_NORM if cfg["allowed"] != 1 else M.RULE_FP64)
     Y = torch.empty((cfg["draws"], n), dtype=torch.float32, device="cuda") if cfg["draws"] else None
     B = torch.empty((cfg["rhs"], n), dtype=torch.float64, device="cuda") if cfg["rhs"] else None
     Brhs = torch.tensor(np.ascontiguousarray(synth.rhs(n, cfg["rhs"]).T), device="cuda") if cfg["rhs"] else None
@@ -167,6 +192,18 @@ def main():
             t64.append(M.mpchol_get_stats(h)["t_factor_ms"])
             log(f"  fp64: t_factor={t64[-1]:.1f} ms  {flops / t64[-1] / 1e9:.2f} TFLOP/s")
         fp64 = flops / statistics.median(t64) / 1e9
+    compare = {}
+    for name in [c for c in args.compare.split(",") if c]:
+        M.mpchol_set_generator(h, sigma, x, rho, nugget)
+        cm = M.mpchol_precision_map(h, RULES[name], eps)
+        info = M.mpchol_factor(h)
+        stc = M.mpchol_get_stats(h)
+        bec = M.mpchol_backward_error(h) if info == 0 else None
+        compare[name] = {"t_factor_ms": round(stc["t_factor_ms"], 1),
+                         "tflops": round(flops / stc["t_factor_ms"] / 1e9, 3), "backward_error": bec,
+                         "fallbacks": stc["fallbacks"], "rule_used": stc["rule_used"],
+                         "tiles_per_class": [int(v) for v in stc["tiles_per_class"]]}
+        log(f"  compare {name}: {compare[name]}")
     M.mpchol_destroy(h)
 
     cpu, ld_ref = (None, None)
@@ -182,13 +219,16 @@ def main():
                  ("/fp8-e4m3" if cfg["allowed"] & 8 else ""),
         "data": "synthetic",
         "config": {"workload": f"SH covariance L={L} (N={n}), tile {tile}, rho={rho}, nugget 1e-8, "
-                               f"norm rule eps={eps}, classes {cfg['label']}",
+                               f"{[k for k, v in RULES.items() if v == rule][0]} rule eps={eps}, classes {cfg['label']}",
                    "N": n, "tile": tile, "nt": nt, "rho": rho, "eps": eps,
                    "step": "generate+norms+map+factor+logdet" + ("+1000 draws" if cfg["draws"] else "")
                            + (f"+solve({cfg['rhs']} rhs)" if cfg["rhs"] else "")},
         "t_factor_ms": round(t_med, 2),
         "fp64_tflops": None if fp64 is None else round(fp64, 3),
         "speedup_vs_fp64": None if fp64 is None else round(value / fp64, 3),
+        "rule": [k for k, v in RULES.items() if v == rule][0],
+        "fallbacks": st["fallbacks"],
+        "compare": compare or None,
         "backward_error": berr,
         "logdet_rel_err": None if ld_ref is None else abs(ld - ld_ref) / abs(ld_ref),
         "tiles_per_class": {CLASS[c]: int(hist[c]) for c in range(4)},

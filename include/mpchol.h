@@ -76,7 +76,8 @@ typedef struct mpchol_opts {
     int32_t band;        /* tiles with |I-J| <= band stay FP64 under NORM, BAND and LEARNED (default 1) */
     uint32_t allowed;    /* bit mask of allowed classes (bit p for class p); FP64 is always allowed */
     int32_t band_variant;/* MPCHOL_BAND_* used by MPCHOL_RULE_BAND */
-    int32_t verify;      /* LEARNED rule: check the backward error after factor and fall back on violation */
+    int32_t verify;      /* LEARNED rule: check the backward error after factor and fall back on violation:
+                            0 off, 1 exact FP64 residual, 2 randomized estimate (64 probes, 3-sigma margin) */
     double verify_eps;   /* backward-error budget used by verify */
     int32_t profile;     /* nonzero: time every update-GEMM launch with events (adds event overhead) */
 } mpchol_opts;
@@ -170,6 +171,14 @@ int mpchol_normal_draws(mpchol_t h, int64_t count, uint64_t seed, float *z, uint
  * doubles, column-major) receives the squared residual norm of each lower
  * tile (strict-lower entries of a diagonal tile counted twice).  Synchronizes. */
 int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2);
+
+/* Randomized estimate of the same ratio: with `sets` x 32 probe vectors v
+ * (N(0,1) entries from Philox with key derived from `seed`),
+ * ||Sigma - L L^T||_F^2 = E ||(Sigma - L L^T) v||^2, and each product costs
+ * O(N^2) (Sigma v from the generator or the kept copy, then L (L^T v) with
+ * the stored tiles widened to FP64).  Relative standard deviation of the
+ * estimate about 1/sqrt(64 sets).  Synchronizes. */
+int mpchol_backward_error_estimate(mpchol_t h, int32_t sets, uint64_t seed, double *est);
 
 /* Copy the factor's represented values into device L (n x n FP64, ldl >= n;
  * the strict upper part is zeroed).  Valid after a successful factor. */

@@ -55,6 +55,12 @@ void launch_update(const Tiles &T, const Panel &P, int q, const int32_t *items, 
 void launch_residual_items(const Tiles &T, const Source &S, const int32_t *items, int nitems, double *partial,
                            double *tile_res2, hipStream_t st);
 
+// ---- backward-error estimate (k_estimate.hip): scratch 3*nt*b*probes doubles,
+// zbuf n*probes floats; *out = sum over the probes of ||(Sigma - L L^T) v||^2
+void launch_estimate(const Tiles &T, const Source &S, uint64_t seed, double *scratch, float *zbuf, double *out,
+                     hipStream_t st);
+int estimate_probes();
+
 // ---- solve, sample (k_apply.hip)
 void launch_solve(const Tiles &T, double *B, int64_t ldb, int nrhs, hipStream_t st);
 void launch_normal_draws(uint64_t seed, int64_t count, float *z, uint32_t *raw, hipStream_t st);

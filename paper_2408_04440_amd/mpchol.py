@@ -81,6 +81,7 @@ def lib():
             "mpchol_sample_z": (C.c_int, [vp, i32, vp, i64, vp, i64]),
             "mpchol_normal_draws": (C.c_int, [vp, i64, u64, vp, vp]),
             "mpchol_backward_error": (C.c_int, [vp, C.POINTER(d), vp]),
+            "mpchol_backward_error_estimate": (C.c_int, [vp, i32, u64, C.POINTER(d)]),
             "mpchol_get_factor": (C.c_int, [vp, vp, i64]),
             "mpchol_get_tile_scales": (C.c_int, [vp, vp]),
             "mpchol_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
@@ -240,6 +241,13 @@ def mpchol_backward_error(h, tiles=False, nt=None):
     _chk(lib().mpchol_backward_error(h, C.byref(be), None if tr is None else tr.ctypes.data_as(C.c_void_p)),
          "mpchol_backward_error")
     return (be.value, tr) if tiles else be.value
+
+
+def mpchol_backward_error_estimate(h, sets=2, seed=7):
+    be = C.c_double(0.0)
+    _chk(lib().mpchol_backward_error_estimate(h, int(sets), C.c_uint64(seed), C.byref(be)),
+         "mpchol_backward_error_estimate")
+    return be.value
 
 
 def mpchol_get_factor(h, L, n):

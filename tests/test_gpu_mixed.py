@@ -187,3 +187,45 @@ def test_full_size_fp8_129600(orc):
     assert np.all(hist > 0)
     assert be <= 1e-9
     assert abs(ld - ref) / abs(ref) <= 1e-8
+
+
+@pytest.mark.parametrize("L,tile,eps", [(32, 128, 1e-6), (32, 128, 1e-4), (48, 256, 1e-5), (30, 128, 1e-9)])
+def test_backward_error_estimate(L, tile, eps):
+    """The randomized estimate (64 probes) against the exact FP64 residual:
+    its relative standard deviation is about 1/sqrt(2*64) = 0.09, so within
+    4 sigma of the exact value."""
+    n = L * L
+    sigma, x = synth.workload(L)
+    mod = M()
+    h = mod.mpchol_create(n, tile)
+    try:
+        mod.mpchol_set_generator(h, sigma, x, 5.0, 1e-8)
+        mod.mpchol_precision_map(h, mod.RULE_NORM, eps)
+        assert mod.mpchol_factor(h) == 0
+        be = mod.mpchol_backward_error(h)
+        est = mod.mpchol_backward_error_estimate(h, 2, 11)
+    finally:
+        mod.mpchol_destroy(h)
+    log(f"  estimate n={n} eps={eps}: exact={be:.3e} estimate={est:.3e}")
+    assert abs(est / be - 1.0) <= 4.0 / np.sqrt(2.0 * 64)
+
+
+def test_verify_with_estimator_falls_back():
+    """verify = 2: the estimator judges the learned map; all-FP8 weights fail it."""
+    L, tile = 32, 128
+    n = L * L
+    sigma, x = synth.workload(L)
+    P = np.zeros(4996, np.float32)
+    P[-1] = 100.0
+    mod = M()
+    h = mod.mpchol_create(n, tile, verify=2, verify_eps=1e-9)
+    try:
+        mod.mpchol_set_generator(h, sigma, x, 5.0, 1e-8)
+        mod.mpchol_selector_set(h, P)
+        mod.mpchol_precision_map(h, mod.RULE_LEARNED, 1e-9)
+        assert mod.mpchol_factor(h) == 0
+        st = mod.mpchol_get_stats(h)
+        be = mod.mpchol_backward_error(h)
+    finally:
+        mod.mpchol_destroy(h)
+    assert st["fallbacks"] >= 1 and be <= 1e-9
