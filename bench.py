@@ -44,6 +44,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+UPDATE_SOURCES = ["paper_2408_04440_amd/csrc/gemm_core.h", "paper_2408_04440_amd/csrc/k_factor.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_c4.json")
+
+
+def update_kernel_hash():
+    """Hash of the update kernels' sources: counter-based traffic numbers are
+    only reported while the kernels are the ones they were measured on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in UPDATE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != update_kernel_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
 def cpu_baseline(sigma, x, rho, nugget, target_s=15.0):
     """The oracle's plain FP64 Cholesky timed on the host on a bounded sample
     (the leading n_s x n_s block of the same covariance), plus the O(N)
@@ -175,7 +206,9 @@ def main():
     ach = st["gemm_flops"][q] / st["t_gemm_ms"][q] / 1e9 if st["t_gemm_ms"][q] > 0 else 0.0
     t_roof = sum(st["flops_per_class"][c] / (PEAK[c] * 1e12) for c in range(4))
     roofline = {"bound": "mfma", "kernel": f"update_{CLASS[q]}", "achieved": round(ach, 3), "peak": PEAK[q],
-                "unit": "TFLOP/s", "frac": round(ach / PEAK[q], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK[q], 4),
+                "traffic": measured_traffic(f"update_{CLASS[q]}") if args.config == "c4" else None,
+                "algorithmic_flops_per_launch": st["gemm_flops"][q] / max(st["gemm_launches"][q], 1),
                 "launches": st["gemm_launches"][q],
                 "mixed_roofline_frac": round(t_roof / (t_med / 1e3), 4),
                 "fp64_peak_frac": round(value / PEAK[0], 4)}

@@ -68,12 +68,13 @@ void launch_normal_matrix(uint64_t seed, int64_t n, int ndraws, float *Z, int64_
 }
 
 // ---------------------------------------------------------------- Y = L Z
-// One 128 x 128 block of Y per workgroup: rows of tile row I, columns of
-// draws; sum over K <= I of L_IK Z_K with FP32 MFMA, each stored tile widened
-// (exactly, or rounded to FP32 for FP64 tiles) on its way into LDS.
-constexpr int SB = 128, SK = 16, SLD = SB + 16;
+// One 128 x 128 block of Y per workgroup of 16 waves (32 x 32 each): rows of
+// tile row I, columns of draws; sum over K <= I of L_IK Z_K with FP32 MFMA,
+// each stored tile widened (exactly, or rounded to FP32 for FP64 tiles) on its
+// way into LDS.
+constexpr int SB = 128, SK = 16, SLD = SB + 4, SW = 4, SNT = 64 * SW * SW, SPER = SK * SB / SNT;
 
-__global__ __launch_bounds__(256) void lower_apply_kernel(Tiles T, const float *Z, int64_t ldz, float *Y, int64_t ldy,
+__global__ __launch_bounds__(SNT) void lower_apply_kernel(Tiles T, const float *Z, int64_t ldz, float *Y, int64_t ldy,
                                                           int ndraws)
 {
     __shared__ float As[2][SK][SLD], Bs[2][SK][SLD];
@@ -81,22 +82,23 @@ __global__ __launch_bounds__(256) void lower_apply_kernel(Tiles T, const float *
     const int I = blockIdx.x / nsub, tm = blockIdx.x % nsub;
     const int s0 = blockIdx.y * SB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1, gi = lane & 15, gg = lane >> 4;
-    float4_t acc[4][4];
+    const int wm = wave % SW, wn = wave / SW, gi = lane & 15, gg = lane >> 4;
+    constexpr int WT = SB / SW;
+    float4_t acc[2][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
+        for (int n = 0; n < 2; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
     const int nkt = b / SK;
-    float ra[8], rb[8];
+    float ra[SPER], rb[SPER];
     for (int K = 0; K <= I; ++K) {
         const int ca = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
         const int ta = T.tscale[I + (int64_t)K * T.nt];
         const char *sa = T.slots + tile_index(I, K) * T.slot_bytes;
         auto gload = [&](int kt) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                int e = tid + 256 * c;
+            for (int c = 0; c < SPER; ++c) {
+                int e = tid + SNT * c;
                 int r = e % SB, col = e / SB;
                 ra[c] = (float)load_stored(sa, ca, T.lo16, ta, (int64_t)(tm * SB + r) + (int64_t)(kt * SK + col) * b);
                 int kk = e % SK, s = e / SK;
@@ -106,8 +108,8 @@ __global__ __launch_bounds__(256) void lower_apply_kernel(Tiles T, const float *
         };
         auto sstore = [&](int buf) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                int e = tid + 256 * c;
+            for (int c = 0; c < SPER; ++c) {
+                int e = tid + SNT * c;
                 As[buf][e / SB][e % SB] = ra[c];
                 Bs[buf][e % SK][e / SK] = rb[c];
             }
@@ -120,15 +122,15 @@ __global__ __launch_bounds__(256) void lower_apply_kernel(Tiles T, const float *
             if (kt + 1 < nkt) gload(kt + 1);
 #pragma unroll
             for (int s = 0; s < SK / 4; ++s) {
-                float fa[4], fb[4];
+                float fa[2], fb[2];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) fa[m] = As[cur][s * 4 + gg][wm * 64 + m * 16 + gi];
+                for (int m = 0; m < 2; ++m) fa[m] = As[cur][s * 4 + gg][wm * WT + m * 16 + gi];
 #pragma unroll
-                for (int n = 0; n < 4; ++n) fb[n] = Bs[cur][s * 4 + gg][wn * 64 + n * 16 + gi];
+                for (int n = 0; n < 2; ++n) fb[n] = Bs[cur][s * 4 + gg][wn * WT + n * 16 + gi];
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < 2; ++m)
 #pragma unroll
-                    for (int n = 0; n < 4; ++n)
+                    for (int n = 0; n < 2; ++n)
                         acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[m], fb[n], acc[m][n], 0, 0, 0);
             }
             if (kt + 1 < nkt) sstore(cur ^ 1);
@@ -136,13 +138,13 @@ __global__ __launch_bounds__(256) void lower_apply_kernel(Tiles T, const float *
         }
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n)
+        for (int n = 0; n < 2; ++n)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int64_t i = (int64_t)I * b + tm * SB + wm * 64 + m * 16 + 4 * gg + v;
-                int s = s0 + wn * 64 + n * 16 + gi;
+                int64_t i = (int64_t)I * b + tm * SB + wm * WT + m * 16 + 4 * gg + v;
+                int s = s0 + wn * WT + n * 16 + gi;
                 if (i < T.n && s < ndraws) Y[i + (int64_t)s * ldy] = acc[m][n][v];
             }
 }
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(256) void lower_apply_kernel(Tiles T, const float *
 void launch_lower_apply(const Tiles &T, const float *Z, int64_t ldz, float *Y, int64_t ldy, int ndraws, hipStream_t st)
 {
     dim3 grid(T.nt * (T.b / SB), (ndraws + SB - 1) / SB);
-    lower_apply_kernel<<<grid, 256, 0, st>>>(T, Z, ldz, Y, ldy, ndraws);
+    lower_apply_kernel<<<grid, SNT, 0, st>>>(T, Z, ldz, Y, ldy, ndraws);
 }
 
 // ---------------------------------------------------------------- solve

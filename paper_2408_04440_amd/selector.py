@@ -52,9 +52,13 @@ def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, 
 
 
 def class_weights(y) -> np.ndarray:
+    """Inverse-frequency weights (mean 1 over present classes), clipped to
+    [0.25, 8]; absent classes get 0."""
     cnt = np.bincount(y, minlength=4).astype(np.float64)
-    w = np.where(cnt > 0, cnt.sum() / np.maximum(cnt, 1) / 4.0, 0.0)
-    return np.clip(w, 0.25, 8.0)
+    present = cnt > 0
+    w = np.zeros(4)
+    w[present] = np.clip(cnt.sum() / cnt[present] / present.sum(), 0.25, 8.0)
+    return w
 
 
 def train(X, y, steps=600, lr=3e-3, alpha=2.0, seed=3, device=0, log_every=0):
