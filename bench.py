@@ -4,8 +4,10 @@ A step is one pass of the hot path over the synthetic covariance of the
 band-limit-L spherical-harmonic workload: device generation, tile norms and
 the precision map (norm rule), the factorization, the log-determinant and the
 emulation draws L z.  The reported value is the Cholesky rate
-(N^3/3) / t_factor in TFLOP/s, t_factor being the event-timed factorization
-of each timed step (median).  The plain FP64 path (same library, every tile
+(N^3/3) / t_factor in TFLOP/s, t_factor being the wall time of the
+mpchol_factor call of each timed step (median; the call synchronizes and
+includes any verification and fallback); the event-timed kernel span is
+reported beside it.  The plain FP64 path (same library, every tile
 FP64) is timed after the mixed steps for the speedup.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c4]
@@ -149,7 +151,7 @@ def main():
     stream = torch.cuda.current_stream()
     need_w = args.rule == "learned" or "learned" in args.compare
     h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
-                        verify=1 if need_w else 0, verify_eps=eps)
+                        verify=2 if need_w else 0, verify_eps=eps)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
     if need_w:
         from paper_2408_04440_amd import selector as S
@@ -163,7 +165,10 @@ def main():
     def step():
         M.mpchol_set_generator(h, sigma, x, rho, nugget)
         cmap = M.mpchol_precision_map(h, rule, eps)
-        info = M.mpchol_factor(h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = M.mpchol_factor(h)  # synchronizes; includes verification and fallbacks
+        t_call = (time.perf_counter() - t0) * 1e3
         if info:
             raise RuntimeError(f"factorization failed at column {info}")
         ld = M.mpchol_logdet(h)
@@ -173,6 +178,7 @@ def main():
             B.copy_(Brhs)
             M.mpchol_solve(h, B.T, n)
         st = M.mpchol_get_stats(h)
+        st["t_call_ms"] = t_call
         return cmap, ld, st
 
     for w in range(args.warmup):
@@ -183,10 +189,10 @@ def main():
     tf, sts = [], []
     for s in range(args.steps):
         cmap, ld, st = step()
-        tf.append(st["t_factor_ms"])
+        tf.append(st["t_call_ms"])
         sts.append(st)
-        log(f"  step {s}: t_factor={st['t_factor_ms']:.1f} ms  map={st['t_map_ms']:.1f} ms  "
-            f"{flops / st['t_factor_ms'] / 1e9:.2f} TFLOP/s")
+        log(f"  step {s}: factor call={st['t_call_ms']:.1f} ms (kernels {st['t_factor_ms']:.1f} ms, "
+            f"fallbacks {st['fallbacks']})  map={st['t_map_ms']:.1f} ms  {flops / st['t_call_ms'] / 1e9:.2f} TFLOP/s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t_med = statistics.median(tf)
@@ -220,20 +226,25 @@ def main():
         for _ in range(args.fp64_steps):
             M.mpchol_set_generator(h, sigma, x, rho, nugget)
             M.mpchol_precision_map(h, M.RULE_FP64)
+            torch.cuda.synchronize()
+            t640 = time.perf_counter()
             if M.mpchol_factor(h):
                 raise RuntimeError("FP64 factorization failed")
-            t64.append(M.mpchol_get_stats(h)["t_factor_ms"])
+            t64.append((time.perf_counter() - t640) * 1e3)
             log(f"  fp64: t_factor={t64[-1]:.1f} ms  {flops / t64[-1] / 1e9:.2f} TFLOP/s")
         fp64 = flops / statistics.median(t64) / 1e9
     compare = {}
     for name in [c for c in args.compare.split(",") if c]:
         M.mpchol_set_generator(h, sigma, x, rho, nugget)
         cm = M.mpchol_precision_map(h, RULES[name], eps)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
         info = M.mpchol_factor(h)
+        t_call = (time.perf_counter() - tc0) * 1e3
         stc = M.mpchol_get_stats(h)
         bec = M.mpchol_backward_error(h) if info == 0 else None
-        compare[name] = {"t_factor_ms": round(stc["t_factor_ms"], 1),
-                         "tflops": round(flops / stc["t_factor_ms"] / 1e9, 3), "backward_error": bec,
+        compare[name] = {"t_factor_ms": round(t_call, 1), "t_factor_kernels_ms": round(stc["t_factor_ms"], 1),
+                         "tflops": round(flops / t_call / 1e9, 3), "backward_error": bec,
                          "fallbacks": stc["fallbacks"], "rule_used": stc["rule_used"],
                          "tiles_per_class": [int(v) for v in stc["tiles_per_class"]]}
         log(f"  compare {name}: {compare[name]}")
@@ -257,6 +268,7 @@ def main():
                    "step": "generate+norms+map+factor+logdet" + ("+1000 draws" if cfg["draws"] else "")
                            + (f"+solve({cfg['rhs']} rhs)" if cfg["rhs"] else "")},
         "t_factor_ms": round(t_med, 2),
+        "t_factor_kernels_ms": round(st["t_factor_ms"], 2),
         "fp64_tflops": None if fp64 is None else round(fp64, 3),
         "speedup_vs_fp64": None if fp64 is None else round(value / fp64, 3),
         "rule": [k for k, v in RULES.items() if v == rule][0],

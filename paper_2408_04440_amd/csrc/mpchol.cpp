@@ -903,28 +903,47 @@ extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, d
     int rc = compute_norms(h);
     if (rc) return rc;
     const double budget = 0.5 * (eps * h->total_fro) * (eps * h->total_fro);
-    // per-tile squared residual at each class: factor with every eligible tile at that class
-    std::vector<std::vector<double>> res(4, std::vector<double>((size_t)nt * nt, 0.0));
-    std::vector<uint8_t> um((size_t)nt * nt, 0);
+    // Per-tile squared residual at each class: factor with every eligible tile
+    // at that class; if that breaks down, retry with only the tiles the norm
+    // rule puts at that class or lower for targets eps*1e6, eps*1e3, eps (the
+    // others FP64).  Residuals are tile-separable, so the other tiles' classes
+    // barely matter; a tile never measured at a class is not eligible for it.
+    std::vector<std::vector<double>> res(4, std::vector<double>((size_t)nt * nt, INFINITY));
+    std::fill(res[P64].begin(), res[P64].end(), 0.0);
+    std::vector<uint8_t> um((size_t)nt * nt, 0), nm((size_t)nt * nt, 0);
     for (int q = P32; q <= P8; ++q) {
         if (!(h->o.allowed & (1u << q))) continue;
-        for (int J = 0; J < nt; ++J)
-            for (int I = J + 1; I < nt; ++I) um[I + (size_t)J * nt] = (I - J > w) ? (uint8_t)q : 0;
-        rc = apply_map(h, MPCHOL_RULE_USER, eps, um.data());
-        if (rc) return rc;
-        int64_t inf = 0;
-        rc = run_factor(h, &inf);
-        if (rc < 0) return rc;
-        if (rc == MPCHOL_NOT_SPD) {
-            for (auto &v : res[q]) v = INFINITY;  // a breakdown marks this class unusable everywhere
-            continue;
+        const double scales[4] = {0.0, 1e6, 1e3, 1.0};
+        for (int trial = 0; trial < 4; ++trial) {
+            if (trial > 0) rule_norm(h, eps * scales[trial], nm);
+            int cnt = 0;
+            for (int J = 0; J < nt; ++J)
+                for (int I = J + 1; I < nt; ++I) {
+                    size_t t = I + (size_t)J * nt;
+                    bool at_q = (I - J > w) && (trial == 0 || nm[t] >= q);
+                    um[t] = at_q ? (uint8_t)q : 0;
+                    cnt += at_q;
+                }
+            if (cnt == 0) break;
+            rc = apply_map(h, MPCHOL_RULE_USER, eps, um.data());
+            if (rc) return rc;
+            int64_t inf = 0;
+            rc = run_factor(h, &inf);
+            if (rc < 0) return rc;
+            if (rc == MPCHOL_NOT_SPD) continue;
+            std::vector<double> tr((size_t)nt * nt, 0.0);
+            double be = 0;
+            rc = residual(h, &be, tr.data());
+            if (rc) return rc;
+            for (size_t t = 0; t < um.size(); ++t)
+                if (um[t] == q) res[q][t] = tr[t];
+            break;
         }
-        double be = 0;
-        rc = residual(h, &be, res[q].data());
-        if (rc) return rc;
     }
-    // greedy: time weight of tile (I,J) = J updates of 2b^3 flops at the class's MFMA rate
-    const double rate[4] = {78.6, 157.3, 2500.0, 5000.0};
+    // greedy: time weight of tile (I,J) = J updates of 2b^3 flops at the rate
+    // the update kernels reach on MI355X (TFLOP/s; the 16-bit and FP8 classes
+    // are bound by HBM, not by their MFMA peaks)
+    const double rate[4] = {58.0, 130.0, 600.0, 700.0};
     std::vector<uint8_t> cur((size_t)nt * nt, 0);
     double used = 0.0;
     struct Move {
