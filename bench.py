@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--no-berr", action="store_true", help="skip the FP64 residual check")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
-    ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band"],
+    ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
                     help="precision map of the timed steps (default: norm, or fp64 for FP64-only workloads)")
     ap.add_argument("--compare", default="", help="comma list of extra rules timed once after the steps, "
                     "each with its backward error (e.g. norm,learned)")
@@ -147,9 +147,10 @@ def main():
         log(f"  copy calibration: {nb} bytes read, {nb} bytes written by one copy kernel")
         del src, dst
 
-    RULES = {"norm": M.RULE_NORM, "learned": M.RULE_LEARNED, "fp64": M.RULE_FP64, "band": M.RULE_BAND}
+    RULES = {"norm": M.RULE_NORM, "learned": M.RULE_LEARNED, "fp64": M.RULE_FP64, "band": M.RULE_BAND,
+             "learned_unverified": M.RULE_LEARNED}
     stream = torch.cuda.current_stream()
-    need_w = args.rule == "learned" or "learned" in args.compare
+    need_w = (args.rule or "").startswith("learned") or "learned" in args.compare
     h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
                         verify=2 if need_w else 0, verify_eps=eps)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
@@ -235,6 +236,7 @@ def main():
         fp64 = flops / statistics.median(t64) / 1e9
     compare = {}
     for name in [c for c in args.compare.split(",") if c]:
+        M.mpchol_set_verify(h, 0 if name == "learned_unverified" else 2, eps)
         M.mpchol_set_generator(h, sigma, x, rho, nugget)
         cm = M.mpchol_precision_map(h, RULES[name], eps)
         torch.cuda.synchronize()
@@ -246,6 +248,7 @@ def main():
         compare[name] = {"t_factor_ms": round(t_call, 1), "t_factor_kernels_ms": round(stc["t_factor_ms"], 1),
                          "tflops": round(flops / t_call / 1e9, 3), "backward_error": bec,
                          "fallbacks": stc["fallbacks"], "rule_used": stc["rule_used"],
+                         "verify_first": stc["verify_first"],
                          "tiles_per_class": [int(v) for v in stc["tiles_per_class"]]}
         log(f"  compare {name}: {compare[name]}")
     M.mpchol_destroy(h)
@@ -273,6 +276,7 @@ def main():
         "speedup_vs_fp64": None if fp64 is None else round(value / fp64, 3),
         "rule": [k for k, v in RULES.items() if v == rule][0],
         "fallbacks": st["fallbacks"],
+        "verify_first": st["verify_first"],
         "compare": compare or None,
         "backward_error": berr,
         "logdet_rel_err": None if ld_ref is None else abs(ld - ld_ref) / abs(ld_ref),

@@ -96,6 +96,7 @@ typedef struct mpchol_stats {
     double gemm_flops[4];        /* flops of those launches */
     int32_t fallbacks;           /* refactorizations made by verify */
     int32_t rule_used;           /* rule of the map the last factor ran with */
+    double verify_first;         /* backward error (exact or estimated) of the first map verify judged; -1 if none */
 } mpchol_stats;
 
 /* Default options: device 0, null stream, FP16, band 1, all classes allowed. */
@@ -187,6 +188,10 @@ int mpchol_get_factor(mpchol_t h, double *L, int64_t ldl);
 /* Host copy of the per-tile stored scale exponents (NT x NT int32,
  * column-major): tile (I,J) represents values code * 2^-t. */
 int mpchol_get_tile_scales(mpchol_t h, int32_t *t);
+
+/* Change the verification of learned maps (mode 0 off, 1 exact, 2 estimate;
+ * eps the budget) for the following factor calls. */
+int mpchol_set_verify(mpchol_t h, int32_t mode, double eps);
 
 /* Fill *s (synchronizes). */
 int mpchol_get_stats(mpchol_t h, mpchol_stats *s);

@@ -674,6 +674,7 @@ extern "C" int mpchol_factor(mpchol_t h, int64_t *info)
     if (h->state != S_LOADED) return MPCHOL_EORDER;
     HIPCHK(hipSetDevice(h->dev));
     h->stats.fallbacks = 0;
+    h->stats.verify_first = -1.0;
     int64_t inf = 0;
     int rc = run_factor(h, &inf);
     if (rc < 0) return rc;
@@ -688,10 +689,12 @@ extern "C" int mpchol_factor(mpchol_t h, int64_t *info)
                     // three standard deviations of the estimate (1 + 3/sqrt(2*64))
                     int r2 = estimate(h, 2, 0x5EEDu + (uint64_t)f, &be);
                     if (r2) return r2;
+                    if (f == 0) h->stats.verify_first = be;
                     ok = (be * (1.0 + 3.0 / std::sqrt(2.0 * 2 * estimate_probes())) <= h->o.verify_eps);
                 } else {
                     int r2 = residual(h, &be, nullptr);
                     if (r2) return r2;
+                    if (f == 0) h->stats.verify_first = be;
                     ok = (be <= h->o.verify_eps);
                 }
             }
@@ -812,6 +815,14 @@ extern "C" int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2
     if (h->state != S_FACTORED) return MPCHOL_EORDER;
     HIPCHK(hipSetDevice(h->dev));
     return residual(h, berr, tile_res2);
+}
+
+extern "C" int mpchol_set_verify(mpchol_t h, int32_t mode, double eps)
+{
+    if (!h || mode < 0 || mode > 2 || !(eps > 0)) return MPCHOL_EINVAL;
+    h->o.verify = mode;
+    h->o.verify_eps = eps;
+    return MPCHOL_OK;
 }
 
 extern "C" int mpchol_get_stats(mpchol_t h, mpchol_stats *s)

@@ -41,7 +41,8 @@ class Stats(C.Structure):
                 ("flops_per_class", C.c_double * 4), ("total_fro", C.c_double), ("t_map_ms", C.c_double),
                 ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_sample_ms", C.c_double),
                 ("t_residual_ms", C.c_double), ("t_gemm_ms", C.c_double * 4), ("gemm_launches", C.c_int64 * 4),
-                ("gemm_flops", C.c_double * 4), ("fallbacks", C.c_int32), ("rule_used", C.c_int32)]
+                ("gemm_flops", C.c_double * 4), ("fallbacks", C.c_int32), ("rule_used", C.c_int32),
+                ("verify_first", C.c_double)]
 
 
 _lib = None
@@ -85,6 +86,7 @@ def lib():
             "mpchol_get_factor": (C.c_int, [vp, vp, i64]),
             "mpchol_get_tile_scales": (C.c_int, [vp, vp]),
             "mpchol_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
+            "mpchol_set_verify": (C.c_int, [vp, i32, d]),
             "mpchol_strerror": (C.c_char_p, [C.c_int]),
             "mpchol_last_error": (C.c_char_p, []),
             "mpchol_selector_set": (C.c_int, [vp, vp, i64]),
@@ -258,6 +260,10 @@ def mpchol_get_tile_scales(h, nt):
     t = np.zeros((nt, nt), dtype=np.int32, order="F")
     _chk(lib().mpchol_get_tile_scales(h, t.ctypes.data_as(C.c_void_p)), "mpchol_get_tile_scales")
     return t
+
+
+def mpchol_set_verify(h, mode, eps):
+    _chk(lib().mpchol_set_verify(h, int(mode), float(eps)), "mpchol_set_verify")
 
 
 def mpchol_get_stats(h):

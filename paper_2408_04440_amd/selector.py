@@ -31,8 +31,10 @@ def he_uniform_init(seed: int = 3) -> np.ndarray:
     return p.astype(np.float32)
 
 
-def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, device=0):
-    """(features [m x 8], labels [m]) of the off-band tiles of one synthetic matrix."""
+def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, device=0, label_eps=None):
+    """(features [m x 8], labels [m], verified backward error) of the off-band
+    tiles of one synthetic matrix; labels for the budget of `label_eps`
+    (default eps), features relative to `eps`."""
     import synth
 
     sigma, x = synth.workload(L, seed)
@@ -41,7 +43,7 @@ def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, 
     h = M.mpchol_create(n, tile, device=device, lo16=lo16, band=band)
     try:
         M.mpchol_set_generator(h, sigma, x, rho, nugget)
-        labels, berr = M.mpchol_selector_labels(h, eps, nt)
+        labels, berr = M.mpchol_selector_labels(h, eps if label_eps is None else label_eps, nt)
         feats = M.mpchol_selector_features(h, eps, nt)
     finally:
         M.mpchol_destroy(h)

@@ -217,3 +217,44 @@ def test_labels_train_apply_small(orc):
         assert be <= eps
     gain = res[mod.RULE_NORM][1] / res[mod.RULE_LEARNED][1]
     log(f"  learned vs norm rule modelled speedup: {gain:.3f}")
+
+
+@pytest.mark.gpu
+def test_shipped_weights_gain_on_held_out_matrix(orc):
+    """The committed selector weights on a matrix outside their training set
+    (band limit 192, seed 11): the learned map passes the estimator check
+    without a fallback, keeps the budget under the exact residual, and needs
+    less peak-weighted time than the norm rule's map."""
+    import paper_2408_04440_amd.selector as S
+
+    eps = 1e-9
+    L, tile, rho = 192, 512, 5.0
+    n = L * L
+    nt = (n + tile - 1) // tile
+    sigma, x = synth.workload(L, 11)
+    mod = M()
+    params = S.load()
+    peaks = np.array([78.6, 157.3, 2500.0, 5000.0])
+    res = {}
+    for rule in (mod.RULE_NORM, mod.RULE_LEARNED):
+        h = mod.mpchol_create(n, tile, verify=2, verify_eps=eps)
+        try:
+            mod.mpchol_set_generator(h, sigma, x, rho, 1e-8)
+            mod.mpchol_selector_set(h, params)
+            mp = mod.mpchol_precision_map(h, rule, eps)
+            assert mod.mpchol_factor(h) == 0
+            st = mod.mpchol_get_stats(h)
+            be = mod.mpchol_backward_error(h)
+        finally:
+            mod.mpchol_destroy(h)
+        model_t = float(np.sum(np.array(st["flops_per_class"]) / peaks))
+        hist = np.bincount(mp[np.tril_indices(nt, -1)], minlength=4)
+        res[rule] = (be, model_t, st["fallbacks"], st["t_factor_ms"])
+        log(f"  rule={rule}: be={be:.2e} modelled={model_t:.3e} s factor={st['t_factor_ms']:.1f} ms "
+            f"fallbacks={st['fallbacks']} verify={st['verify_first']:.2e} hist={hist}")
+        assert be <= eps
+    assert res[mod.RULE_LEARNED][2] == 0
+    gain = res[mod.RULE_NORM][1] / res[mod.RULE_LEARNED][1]
+    log(f"  learned vs norm: modelled gain {gain:.3f}, measured factor "
+        f"{res[mod.RULE_NORM][3]:.1f} -> {res[mod.RULE_LEARNED][3]:.1f} ms")
+    assert gain > 1.0
