@@ -233,8 +233,12 @@ __global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const
         for (int n = 0; n < S::NB; ++n)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[m][n][v] = 0;
-    cm_block<T, BM, BN, BK, WM, WN>(panel + I * bb + tm * BM, b, panel + J * bb + tn * BN, b, b, acc,
-                                    (T *)smem_raw);
+    // FP64 accumulators hold four rows 4 apart per lane; with the operands
+    // swapped each lane owns one row instead, so the stores below cover
+    // 16 contiguous doubles per column.  FP32 rows are already contiguous.
+    constexpr bool SWAP = sizeof(T) == 8;
+    cm_block<T, BM, BN, BK, WM, WN, SWAP>(panel + I * bb + tm * BM, b, panel + J * bb + tn * BN, b, b, acc,
+                                          (T *)smem_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
     T *C = (T *)(Tt.slots + tile_index(I, J) * Tt.slot_bytes) + tm * BM + (int64_t)tn * BN * b;
@@ -242,10 +246,17 @@ __global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const
     for (int m = 0; m < S::MB; ++m)
 #pragma unroll
         for (int n = 0; n < S::NB; ++n) {
-            int r = wm * (BM / WM) + m * 16, c = wn * (BN / WN) + n * 16 + gi;
-            T *p = C + r + (int64_t)c * b;
+            if (SWAP) {
+                int r = wm * (BM / WM) + m * 16 + gi, c = wn * (BN / WN) + n * 16;
+                T *p = C + r + (int64_t)c * b;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) p[acc_row<T>(gg, v)] -= acc[m][n][v];
+                for (int v = 0; v < 4; ++v) p[(int64_t)acc_row<T>(gg, v) * b] -= acc[m][n][v];
+            } else {
+                int r = wm * (BM / WM) + m * 16, c = wn * (BN / WN) + n * 16 + gi;
+                T *p = C + r + (int64_t)c * b;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) p[acc_row<T>(gg, v)] -= acc[m][n][v];
+            }
         }
 }
 
