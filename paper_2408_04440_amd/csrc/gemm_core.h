@@ -128,100 +128,6 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
     }
 }
 
-// ---------------------------------------------------------------- cm32 (FP32, 32x32x2 MFMA)
-// Same staging as cm_block, multiplied with the 32 x 32 x 2 FP32 MFMA, which
-// does twice the work per operand element of 16 x 16 x 4.  Operands are
-// passed swapped, so lane l owns row (l % 32) of each 32 x 32 sub-tile and
-// accumulator element v its column 8 (v / 4) + 4 (l / 32) + v % 4.
-// MFMA 32x32x2 lane layout: a = A[l % 32][l / 32], b = B[l / 32][l % 32],
-// d[v] = D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
-
-template <int BM, int BN, int BK, int WM, int WN>
-struct CM32Shape {
-    static constexpr int NTH = 64 * WM * WN;
-    static constexpr int VEC = 4;
-    static constexpr int LDM = BM + 32, LDN = BN + 32;  // the two lane halves 32 banks apart
-    static constexpr int CHA = BK * BM / VEC, CHB = BK * BN / VEC;
-    static constexpr int CA = (CHA + NTH - 1) / NTH, CB = (CHB + NTH - 1) / NTH;
-    static constexpr int MB = BM / WM / 32, NB = BN / WN / 32;
-    static constexpr size_t SMEM = sizeof(float) * (size_t)2 * BK * (LDM + LDN);
-    static_assert((CHA % NTH == 0 || CHA < NTH) && (CHB % NTH == 0 || CHB < NTH), "load split");
-    static_assert(BK % 2 == 0 && MB >= 1 && NB >= 1, "shape");
-};
-
-// Column (within a 32 x 32 sub-tile) of element v of lane l's swapped accumulator.
-__device__ inline int acc32_col(int l, int v) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
-
-template <int BM, int BN, int BK, int WM, int WN>
-__device__ inline void cm32_block(const float *__restrict__ A, int64_t lda, const float *__restrict__ B, int64_t ldb,
-                                  int K, f32x16_t (&acc)[CM32Shape<BM, BN, BK, WM, WN>::MB][CM32Shape<BM, BN, BK, WM, WN>::NB],
-                                  float *smem)
-{
-    typedef CM32Shape<BM, BN, BK, WM, WN> S;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
-    const int li = lane & 31, lg = lane >> 5;
-    float *As = smem;                    // [2][BK][LDM]
-    float *Bs = smem + 2 * BK * S::LDM;  // [2][BK][LDN]
-    u32x4 ra[S::CA], rb[S::CB];
-    const int nk = K / BK;
-
-    auto gload = [&](int kt) {
-#pragma unroll
-        for (int c = 0; c < S::CA; ++c) {
-            int ch = tid + S::NTH * c;
-            int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
-            if (ch < S::CHA) ra[c] = *(const u32x4 *)(A + r + (int64_t)(kt * BK + col) * lda);
-        }
-#pragma unroll
-        for (int c = 0; c < S::CB; ++c) {
-            int ch = tid + S::NTH * c;
-            int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
-            if (ch < S::CHB) rb[c] = *(const u32x4 *)(B + r + (int64_t)(kt * BK + col) * ldb);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int c = 0; c < S::CA; ++c) {
-            int ch = tid + S::NTH * c;
-            int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
-            if (ch < S::CHA) *(u32x4 *)(As + (buf * BK + col) * S::LDM + r) = ra[c];
-        }
-#pragma unroll
-        for (int c = 0; c < S::CB; ++c) {
-            int ch = tid + S::NTH * c;
-            int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
-            if (ch < S::CHB) *(u32x4 *)(Bs + (buf * BK + col) * S::LDN + r) = rb[c];
-        }
-    };
-
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload(kt + 1);
-        const float *as = As + cur * BK * S::LDM + wm * (BM / WM) + li;
-        const float *bs = Bs + cur * BK * S::LDN + wn * (BN / WN) + li;
-#pragma unroll
-        for (int s = 0; s < BK / 2; ++s) {
-            float fa[S::MB], fb[S::NB];
-#pragma unroll
-            for (int m = 0; m < S::MB; ++m) fa[m] = as[(s * 2 + lg) * S::LDM + m * 32];
-#pragma unroll
-            for (int n = 0; n < S::NB; ++n) fb[n] = bs[(s * 2 + lg) * S::LDN + n * 32];
-#pragma unroll
-            for (int m = 0; m < S::MB; ++m)
-#pragma unroll
-                for (int n = 0; n < S::NB; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(fb[n], fa[m], acc[m][n], 0, 0, 0);
-        }
-        if (kt + 1 < nk) sstore(cur ^ 1);
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------- rm (FP16 / BF16 / FP8)
 enum { RM_F16 = 0, RM_BF16 = 1, RM_FP8 = 2 };
 
