@@ -4,15 +4,17 @@
 //   * "cm" (FP64, FP32): A(r, k) = A[r + k*lda]  (a column-major tile: rows
 //     contiguous for each k), MFMA 16x16x4 (one element per lane);
 //   * "rm" (FP16, BF16, FP8): A(r, k) = A[r*lda + k]  (k contiguous), MFMA
-//     16x16x32 (eight elements per lane), FP32 accumulation.
-// 256 threads = 4 waves in a 2 x 2 grid; each wave owns (BM/2) x (BN/2) of the
-// block as (BM/32) x (BN/32) MFMA tiles of 16 x 16.  Operands are staged
-// through double-buffered LDS, the next K slice is fetched into registers
-// while the current one is multiplied.
+//     16x16x32 for FP16/BF16 (eight elements per lane) and 16x16x128 for FP8
+//     (32 elements per lane), FP32 accumulation.
+// WM x WN waves per block; each wave owns (BM/WM) x (BN/WN) of the block as
+// 16 x 16 MFMA tiles.  Operands are staged through double-buffered LDS, the
+// next K slice is fetched into registers while the current one is multiplied.
 //
 // MFMA lane layout used (lane l = 0..63, g = l / 16, i = l % 16):
 //   16x16x4 :  a = A[i][g],          b = B[g][i]
 //   16x16x32:  a[j] = A[i][8g + j],  b[j] = B[8g + j][i]   (j = 0..7)
+//   16x16x128 (8-bit): 32 K elements of row i / column i per lane, the same
+//              K assignment for a and b
 //   result  :  d[v] = D[4g + v][i]   (v = 0..3) for the FP32-accumulating forms,
 //              d[v] = D[g + 4v][i]   for 16x16x4 FP64 (64-bit accumulator registers)
 #pragma once
@@ -135,6 +137,7 @@ template <int KIND> struct RM;
 template <> struct RM<RM_F16> {
     typedef uint16_t T;
     typedef u32x4 frag_t;  // 8 halves
+    static constexpr int KSTEP = 32;
     __device__ static inline float4_t mfma(frag_t a, frag_t b, float4_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(half8_t, a), __builtin_bit_cast(half8_t, b), c, 0, 0, 0);
@@ -143,17 +146,25 @@ template <> struct RM<RM_F16> {
 template <> struct RM<RM_BF16> {
     typedef uint16_t T;
     typedef u32x4 frag_t;
+    static constexpr int KSTEP = 32;
     __device__ static inline float4_t mfma(frag_t a, frag_t b, float4_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
     }
 };
+typedef int32_t i32x8 __attribute__((ext_vector_type(8)));
+// FP8 E4M3 operands, 16 x 16 x 128 per instruction (format code 0 for both
+// operands, no block scaling: the per-tile power-of-two scales are applied in
+// the epilogue).  Each lane holds 32 consecutive K elements of its row; A and
+// B use the same lane -> K assignment, so the K order inside the instruction
+// does not affect the sum.
 template <> struct RM<RM_FP8> {
     typedef uint8_t T;
-    typedef u32x2 frag_t;  // 8 bytes
+    typedef i32x8 frag_t;  // 32 bytes
+    static constexpr int KSTEP = 128;
     __device__ static inline float4_t mfma(frag_t a, frag_t b, float4_t c)
     {
-        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
     }
 };
 
@@ -169,7 +180,7 @@ struct RMShape {
     static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;
     static constexpr size_t SMEM = (size_t)2 * (BM + BN) * LDB;
     static_assert((CHA % NTH == 0 || CHA < NTH) && (CHB % NTH == 0 || CHB < NTH), "load split");
-    static_assert(BK % 32 == 0 && MB >= 1 && NB >= 1, "shape");
+    static_assert(BK % RM<KIND>::KSTEP == 0 && MB >= 1 && NB >= 1, "shape");
 };
 
 template <int KIND, int BM, int BN, int BK, int WM = 2, int WN = 2>
@@ -227,8 +238,9 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
         const uint8_t *as = As + (cur * BM + wm * (BM / WM) + gi) * S::LDB;
         const uint8_t *bs = Bs + (cur * BN + wn * (BN / WN) + gi) * S::LDB;
 #pragma unroll
-        for (int s = 0; s < BK / 32; ++s) {
-            const int kb = (s * 32 + 8 * gg) * (int)sizeof(T);
+        for (int s = 0; s < BK / RM<KIND>::KSTEP; ++s) {
+            constexpr int KS = RM<KIND>::KSTEP;  // K per instruction; KS / 4 per lane
+            const int kb = (s * KS + (KS / 4) * gg) * (int)sizeof(T);
             F fa[S::MB], fb[S::NB];
 #pragma unroll
             for (int m = 0; m < S::MB; ++m) fa[m] = *(const F *)(as + m * 16 * S::LDB + kb);
