@@ -8,41 +8,58 @@
 namespace mpc {
 
 // ---------------------------------------------------------------- POTRF
-// Right-looking Cholesky of the 64 x 64 block at (j0, j0) of an FP64 tile
-// (column-major, leading dimension b) by one wavefront, the block held in LDS
-// with lane r owning row r: per column, the pivot and the scaled column are
-// read as broadcasts and each lane updates its own row.  A pivot that is not
-// positive (or NaN) records its 1-based global column in *info (minimum over
-// failures); the computation then continues on NaNs and still terminates.
+// Cholesky of the 64 x 64 block at (j0, j0) of an FP64 tile (column-major,
+// leading dimension b) by one wavefront, in four quarters of 16 columns: lane
+// r holds its row of the quarter in registers, first less the earlier
+// quarters' contribution, then right-looking over the quarter's columns with
+// each finished column broadcast through LDS (a[c][r] = L(j0 + r, j0 + c)).
+// A pivot that is not positive (or NaN) records its 1-based global column in
+// *info (minimum over failures); the computation then continues on NaNs and
+// still terminates.  Zeros are written above the diagonal.
+__device__ inline void wave_sync()
+{
+    // orders one wavefront's LDS accesses across lanes (the hardware executes a
+    // wave's LDS instructions in order; this keeps the compiler from moving them)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(64) void potrf_block_kernel(double *tile, int b, int j0, int64_t col0, int64_t n,
                                                          unsigned long long *info)
 {
-    __shared__ double a[64][65];  // a[c][r] = A(j0 + r, j0 + c)
+    __shared__ double a[64][65];
     const int r = threadIdx.x;
     double *base = tile + j0 + (int64_t)j0 * b;
-    for (int j = 0; j < 64; ++j) a[j][r] = base[r + (int64_t)j * b];
-    __syncthreads();
-    for (int c = 0; c < 64; ++c) {
-        const double d = a[c][c];
-        if (r == 0 && !(d > 0.0) && col0 + j0 + c < n) atomicMin(info, (unsigned long long)(col0 + j0 + c + 1));
-        const double piv = sqrt(d);
-        const double l = (r == c) ? piv : a[c][r] / piv;
-        __syncthreads();
-        if (r >= c) a[c][r] = l;
-        __syncthreads();
-        int j = c + 1;
-        for (; j + 3 < 64; j += 4) {
-            const double l0 = a[c][j], l1 = a[c][j + 1], l2 = a[c][j + 2], l3 = a[c][j + 3];
-            if (r >= j) a[j][r] -= l * l0;
-            if (r >= j + 1) a[j + 1][r] -= l * l1;
-            if (r >= j + 2) a[j + 2][r] -= l * l2;
-            if (r >= j + 3) a[j + 3][r] -= l * l3;
+#pragma nounroll
+    for (int h = 0; h < 64; h += 16) {
+        double x[16];  // x[j] = A(j0 + r, j0 + h + j)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = base[r + (int64_t)(h + j) * b];
+        for (int c = 0; c < h; ++c) {  // less L(r, 0:h) L(h+j, 0:h)^T
+            const double lrc = a[c][r];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] -= lrc * a[c][h + j];
         }
-        for (; j < 64; ++j)
-            if (r >= j) a[j][r] -= l * a[c][j];
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            a[h + c][r] = x[c];
+            wave_sync();
+            const double d = a[h + c][h + c];
+            if (r == 0 && !(d > 0.0) && col0 + j0 + h + c < n)
+                atomicMin(info, (unsigned long long)(col0 + j0 + h + c + 1));
+            const double piv = sqrt(d);
+            x[c] = (r == h + c) ? piv : x[c] / piv;
+            wave_sync();
+            a[h + c][r] = x[c];
+            wave_sync();
+#pragma unroll
+            for (int j = c + 1; j < 16; ++j) x[j] -= x[c] * a[h + c][h + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) base[r + (int64_t)(h + j) * b] = (r >= h + j) ? x[j] : 0.0;
+        wave_sync();
     }
-    for (int j = 0; j < 64; ++j) base[r + (int64_t)j * b] = (r >= j) ? a[j][r] : 0.0;
 }
 
 // ---------------------------------------------------------------- TRSM
