@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -60,6 +61,14 @@ def update_kernel_hash():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def verify_value(v):
+    """The first verified map's backward error for the JSON line: None when no
+    map was verified, "breakdown" when its factorization failed."""
+    if v < 0:
+        return None
+    return v if math.isfinite(v) else "breakdown"
 
 
 def measured_traffic(kernel):
@@ -248,7 +257,7 @@ def main():
         compare[name] = {"t_factor_ms": round(t_call, 1), "t_factor_kernels_ms": round(stc["t_factor_ms"], 1),
                          "tflops": round(flops / t_call / 1e9, 3), "backward_error": bec,
                          "fallbacks": stc["fallbacks"], "rule_used": stc["rule_used"],
-                         "verify_first": stc["verify_first"],
+                         "verify_first": verify_value(stc["verify_first"]),
                          "tiles_per_class": [int(v) for v in stc["tiles_per_class"]]}
         log(f"  compare {name}: {compare[name]}")
     M.mpchol_destroy(h)
@@ -276,7 +285,7 @@ def main():
         "speedup_vs_fp64": None if fp64 is None else round(value / fp64, 3),
         "rule": [k for k, v in RULES.items() if v == rule][0],
         "fallbacks": st["fallbacks"],
-        "verify_first": st["verify_first"],
+        "verify_first": verify_value(st["verify_first"]),
         "compare": compare or None,
         "backward_error": berr,
         "logdet_rel_err": None if ld_ref is None else abs(ld - ld_ref) / abs(ld_ref),

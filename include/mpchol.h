@@ -96,7 +96,8 @@ typedef struct mpchol_stats {
     double gemm_flops[4];        /* flops of those launches */
     int32_t fallbacks;           /* refactorizations made by verify */
     int32_t rule_used;           /* rule of the map the last factor ran with */
-    double verify_first;         /* backward error (exact or estimated) of the first map verify judged; -1 if none */
+    double verify_first;         /* backward error (exact or estimated) of the first map verify judged;
+                                    +inf if that map's factorization broke down; -1 if no map was verified */
 } mpchol_stats;
 
 /* Default options: device 0, null stream, FP16, band 1, all classes allowed. */

@@ -60,7 +60,9 @@ struct CMShape {
 // exchanged, so each 16 x 16 accumulator holds the transposed tile: lane i
 // owns row i of the block's sub-tile and element v its column acc_row(g, v)
 // (rows contiguous in memory, so column-major stores coalesce).
-template <typename T, int BM, int BN, int BK, int WM = 2, int WN = 2, bool SWAP = false>
+// PRIO raises the wave's issue priority while it multiplies, so that a wave
+// with operands ready in LDS is not held back by waves still loading.
+template <typename T, int BM, int BN, int BK, int WM = 2, int WN = 2, bool SWAP = false, bool PRIO = false>
 __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb, int K,
                                 typename CM<T>::acc_t (&acc)[CMShape<T, BM, BN, BK, WM, WN>::MB]
                                                               [CMShape<T, BM, BN, BK, WM, WN>::NB],
@@ -112,6 +114,7 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
         if (kt + 1 < nk) gload(kt + 1);
         const T *as = As + cur * BK * S::LDM + wm * (BM / WM) + gi;
         const T *bs = Bs + cur * BK * S::LDN + wn * (BN / WN) + gi;
+        if (PRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
             T fa[S::MB], fb[S::NB];
@@ -125,6 +128,7 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
                 for (int n = 0; n < S::NB; ++n)
                     acc[m][n] = SWAP ? CM<T>::mfma(fb[n], fa[m], acc[m][n]) : CM<T>::mfma(fa[m], fb[n], acc[m][n]);
         }
+        if (PRIO) __builtin_amdgcn_s_setprio(0);
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }

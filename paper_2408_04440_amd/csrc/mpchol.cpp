@@ -699,6 +699,7 @@ extern "C" int mpchol_factor(mpchol_t h, int64_t *info)
                 }
             }
             if (ok) break;
+            if (f == 0 && rc != MPCHOL_OK) h->stats.verify_first = INFINITY;  // the map broke down
             if (f >= 2) {
                 if (info) *info = inf;
                 return rc == MPCHOL_NOT_SPD ? MPCHOL_NOT_SPD : MPCHOL_EBUDGET;

@@ -32,13 +32,14 @@ def test_struct_layouts_match_header(tmp_path):
 
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mpchol.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(mpchol_opts), sizeof(mpchol_stats),'
-                    ' offsetof(mpchol_opts, verify_eps), offsetof(mpchol_stats, t_gemm_ms), offsetof(mpchol_stats, fallbacks));return 0;}\n')
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mpchol_opts), sizeof(mpchol_stats),'
+                    ' offsetof(mpchol_opts, verify_eps), offsetof(mpchol_stats, t_gemm_ms), offsetof(mpchol_stats, fallbacks),'
+                    ' offsetof(mpchol_stats, verify_first));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(M.Opts), C.sizeof(M.Stats), M.Opts.verify_eps.offset, M.Stats.t_gemm_ms.offset,
-            M.Stats.fallbacks.offset]
+            M.Stats.fallbacks.offset, M.Stats.verify_first.offset]
     assert got == want
 
 
@@ -66,6 +67,7 @@ def test_argument_validation_without_gpu():
     assert L.mpchol_logdet(None, None) == -1
     m = C.c_void_p()
     assert L.mpchol_mlp_create(None, 0, None) == -1
+    assert L.mpchol_set_verify(None, 1, C.c_double(1e-9)) == -1
 
 
 def test_product_never_imports_oracle():

@@ -151,7 +151,9 @@ def test_features_and_learned_map(orc, L, tile):
 
 def test_learned_rule_falls_back_to_norm_rule(orc):
     """Weights that send every tile to FP8 violate the budget; with verify on,
-    the factorization is redone under the norm rule and the fallback counted."""
+    the factorization is redone under the norm rule and the fallback counted.
+    With verify switched off (mpchol_set_verify) the same map is kept, and the
+    first verification's backward error is the one the exact residual gives."""
     L, tile = 32, 128
     n = L * L
     sigma, x = synth.workload(L)
@@ -167,12 +169,27 @@ def test_learned_rule_falls_back_to_norm_rule(orc):
         info = mod.mpchol_factor(h)
         st = mod.mpchol_get_stats(h)
         be = mod.mpchol_backward_error(h)
+        # verify off: the all-FP8 map is kept and its error is reported as is
+        mod.mpchol_set_verify(h, 0, 1e-9)
+        mod.mpchol_set_generator(h, sigma, x, 5.0, 1e-8)
+        mod.mpchol_precision_map(h, mod.RULE_LEARNED, 1e-9)
+        info0 = mod.mpchol_factor(h)
+        st0 = mod.mpchol_get_stats(h)
+        be0 = mod.mpchol_backward_error(h) if info0 == 0 else None
+        with pytest.raises(Exception):
+            mod.mpchol_set_verify(h, 3, 1e-9)
     finally:
         mod.mpchol_destroy(h)
-    log(f"  fallback: info={info} fallbacks={st['fallbacks']} rule={st['rule_used']} be={be:.2e}")
+    log(f"  fallback: info={info} fallbacks={st['fallbacks']} rule={st['rule_used']} be={be:.2e} "
+        f"first={st['verify_first']:.2e}; verify off: info={info0} be={be0}")
     assert info == 0
     assert st["fallbacks"] >= 1 and st["rule_used"] in (1, 0)
     assert be <= 1e-9
+    assert st["verify_first"] > 1e-9          # the learned map's own error, which failed the check
+    assert st0["fallbacks"] == 0 and st0["rule_used"] == mod.RULE_LEARNED and st0["verify_first"] == -1.0
+    if info0 == 0:
+        assert be0 > 1e-9
+        assert abs(be0 - st["verify_first"]) <= 1e-6 * be0  # exact residual of the same map, same kernels
 
 
 def test_labels_train_apply_small(orc):
