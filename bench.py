@@ -120,13 +120,16 @@ def main():
     ap.add_argument("--no-berr", action="store_true", help="skip the FP64 residual check")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
+    ap.add_argument("--eps", type=float, default=None, help="override the workload's accuracy threshold")
     ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
                     help="precision map of the timed steps (default: norm, or fp64 for FP64-only workloads)")
-    ap.add_argument("--compare", default="", help="comma list of extra rules timed once after the steps, "
+    ap.add_argument("--compare", default=None, help="comma list of extra rules timed once after the steps, "
                     "each with its backward error (e.g. norm,learned)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB megabytes first (counter calibration)")
     args = ap.parse_args()
+    if args.compare is None:  # the learned selector beside the norm rule on the mixed workloads
+        args.compare = "learned" if args.config in ("c4", "c5") and args.rule in (None, "norm") else ""
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
@@ -141,6 +144,8 @@ def main():
     L, tile, rho, eps = cfg["L"], cfg["tile"], cfg["rho"], cfg["eps"]
     if args.rho is not None:
         rho = args.rho
+    if args.eps is not None:
+        eps = args.eps
     n = L * L
     nugget = 1e-8
     flops = n ** 3 / 3.0
