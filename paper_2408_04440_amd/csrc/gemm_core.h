@@ -56,7 +56,9 @@ struct CMShape {
     static_assert(BK % 4 == 0 && MB >= 1 && NB >= 1, "shape");
 };
 
-// acc += A * B^T over K (K a multiple of BK).  With SWAP the MFMA operands are
+// acc += A * B^T over K (K a multiple of BK); with A2/B2 given, the product
+// continues over a second K range, acc += A2 * B2^T (same leading dimensions),
+// in the same pipelined loop.  With SWAP the MFMA operands are
 // exchanged, so each 16 x 16 accumulator holds the transposed tile: lane i
 // owns row i of the block's sub-tile and element v its column acc_row(g, v)
 // (rows contiguous in memory, so column-major stores coalesce).
@@ -66,7 +68,7 @@ template <typename T, int BM, int BN, int BK, int WM = 2, int WN = 2, bool SWAP 
 __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb, int K,
                                 typename CM<T>::acc_t (&acc)[CMShape<T, BM, BN, BK, WM, WN>::MB]
                                                               [CMShape<T, BM, BN, BK, WM, WN>::NB],
-                                T *smem)
+                                T *smem, const T *__restrict__ A2 = nullptr, const T *__restrict__ B2 = nullptr)
 {
     typedef CMShape<T, BM, BN, BK, WM, WN> S;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -75,20 +77,26 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
     T *As = smem;                       // [2][BK][LDM]
     T *Bs = smem + 2 * BK * S::LDM;     // [2][BK][LDN]
     u32x4 ra[S::CA], rb[S::CB];
-    const int nk = K / BK;
+    const int nk1 = K / BK, nk = A2 ? 2 * nk1 : nk1;
 
     auto gload = [&](int kt) {
+        const T *a = A, *bp = B;
+        if (kt >= nk1) {
+            a = A2;
+            bp = B2;
+            kt -= nk1;
+        }
 #pragma unroll
         for (int c = 0; c < S::CA; ++c) {
             int ch = tid + S::NTH * c;
             int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
-            if (ch < S::CHA) ra[c] = *(const u32x4 *)(A + r + (int64_t)(kt * BK + col) * lda);
+            if (ch < S::CHA) ra[c] = *(const u32x4 *)(a + r + (int64_t)(kt * BK + col) * lda);
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
             int ch = tid + S::NTH * c;
             int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
-            if (ch < S::CHB) rb[c] = *(const u32x4 *)(B + r + (int64_t)(kt * BK + col) * ldb);
+            if (ch < S::CHB) rb[c] = *(const u32x4 *)(bp + r + (int64_t)(kt * BK + col) * ldb);
         }
     };
     auto sstore = [&](int buf) {

@@ -224,12 +224,13 @@ void launch_trsm_panel(const Tiles &T, const Panel &P, int k, hipStream_t st)
 }
 
 // ---------------------------------------------------------------- grouped trailing update
-// One launch per class: every work item (I, J) of the step is a b x b tile
-// update A_IJ -= L_Ik L_Jk^T from the class's panel copies.  Blocks are
+// One launch per class: every work item (I, J) is a b x b tile update
+// A_IJ -= L_Ik L_Jk^T from the class's panel copies, or, for a pair of steps,
+// A_IJ -= L_Ik L_Jk^T + L_I,k+1 L_J,k+1^T with K = 2b in one accumulation.  Blocks are
 // renumbered XCD-aware so the blocks of one item share an L2; an item with
 // I == J (SYRK, always FP64) computes its lower blocks only.
 template <typename T, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const T *panel, const int32_t *items)
+__global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const T *panel0, const T *panel1, const int32_t *items)
 {
     typedef CMShape<T, BM, BN, BK, WM, WN> S;
     extern __shared__ __align__(16) char smem_raw[];
@@ -255,8 +256,10 @@ __global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const
     // 16 contiguous doubles per column.  FP32 rows are already contiguous.
     constexpr bool SWAP = sizeof(T) == 8;
     constexpr bool PRIO = sizeof(T) == 4;  // measured: helps FP32, neutral for FP64
-    cm_block<T, BM, BN, BK, WM, WN, SWAP, PRIO>(panel + I * bb + tm * BM, b, panel + J * bb + tn * BN, b, b, acc,
-                                          (T *)smem_raw);
+    // a pair of steps: K continues over the next panel column
+    cm_block<T, BM, BN, BK, WM, WN, SWAP, PRIO>(panel0 + I * bb + tm * BM, b, panel0 + J * bb + tn * BN, b, b, acc,
+                                                (T *)smem_raw, panel1 ? panel1 + I * bb + tm * BM : nullptr,
+                                                panel1 ? panel1 + J * bb + tn * BN : nullptr);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
     T *C = (T *)(Tt.slots + tile_index(I, J) * Tt.slot_bytes) + tm * BM + (int64_t)tn * BN * b;
@@ -279,8 +282,10 @@ __global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const typename RM<KIND>::T *panel,
-                                                                 const int32_t *pscale, int q, const int32_t *items)
+__global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const typename RM<KIND>::T *panel0,
+                                                                 const int32_t *pscale0,
+                                                                 const typename RM<KIND>::T *panel1,
+                                                                 const int32_t *pscale1, int q, const int32_t *items)
 {
     typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
     extern __shared__ __align__(16) char smem_raw[];
@@ -298,9 +303,39 @@ __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const
     for (int m = 0; m < S::MB; ++m)
 #pragma unroll
         for (int n = 0; n < S::NB; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    rm_block<KIND, BM, BN, BK, WM, WN>(panel + I * bb + (int64_t)tm * BM * b, b, panel + J * bb + (int64_t)tn * BN * b,
-                                       b, b, acc, (uint8_t *)smem_raw);
-    const int tsum = pscale[I * 4 + q] + pscale[J * 4 + q];
+    // Scaled copies: product = acc * 2^-(t_I + t_J).  For a pair of steps the
+    // step with the larger exponent sum (smaller values) is accumulated first
+    // and the accumulator rescaled down to the other step's exponent, which is
+    // exact and cannot overflow; the second product then adds at that scale.
+    const typename RM<KIND>::T *pa = panel0, *pb = panel1;
+    int tsum = pscale0[I * 4 + q] + pscale0[J * 4 + q];
+    int t2 = 0;
+    if (panel1) {
+        t2 = pscale1[I * 4 + q] + pscale1[J * 4 + q];
+        if (t2 > tsum) {
+            pa = panel1;
+            pb = panel0;
+            const int t = tsum;
+            tsum = t2;
+            t2 = t;
+        }
+    }
+    const int npan = pb ? 2 : 1;
+#pragma nounroll
+    for (int h = 0; h < npan; ++h) {
+        const typename RM<KIND>::T *pn = h ? pb : pa;
+        if (h) {
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                for (int n = 0; n < S::NB; ++n)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[m][n][v] = ldexpf(acc[m][n][v], t2 - tsum);
+            tsum = t2;
+        }
+        rm_block<KIND, BM, BN, BK, WM, WN>(pn + I * bb + (int64_t)tm * BM * b, b, pn + J * bb + (int64_t)tn * BN * b, b,
+                                           b, acc, (uint8_t *)smem_raw);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
     float *C = (float *)(Tt.slots + tile_index(I, J) * Tt.slot_bytes) + tm * BM + (int64_t)tn * BN * b;
@@ -316,7 +351,8 @@ __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
-static void launch_cm(const Tiles &T_, const T *panel, const int32_t *items, int nitems, hipStream_t st)
+static void launch_cm(const Tiles &T_, const T *panel0, const T *panel1, const int32_t *items, int nitems,
+                      hipStream_t st)
 {
     typedef CMShape<T, BM, BN, BK, WM, WN> S;
     auto k = update_cm_kernel<T, BM, BN, BK, WM, WN>;
@@ -326,12 +362,13 @@ static void launch_cm(const Tiles &T_, const T *panel, const int32_t *items, int
         attr = true;
     }
     const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
-    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel, items);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel0, panel1, items);
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN>
-static void launch_rm(const Tiles &T_, const typename RM<KIND>::T *panel, const int32_t *pscale, int q,
-                      const int32_t *items, int nitems, hipStream_t st)
+static void launch_rm(const Tiles &T_, const typename RM<KIND>::T *panel0, const int32_t *pscale0,
+                      const typename RM<KIND>::T *panel1, const int32_t *pscale1, int q, const int32_t *items,
+                      int nitems, hipStream_t st)
 {
     typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
     auto k = update_rm_kernel<KIND, BM, BN, BK, WM, WN>;
@@ -341,33 +378,44 @@ static void launch_rm(const Tiles &T_, const typename RM<KIND>::T *panel, const 
         attr = true;
     }
     const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
-    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel, pscale, q, items);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel0, pscale0, panel1, pscale1, q, items);
 }
 
 // Block shapes per class from a sweep on MI355X (1024 x 1024 tiles):
 // FP64 128 x 128 with 16 waves of 32 x 32, FP32 256 x 128 with 8 waves,
 // FP16/BF16 256 x 256 with 16 waves, FP8 128 x 128 with 4 waves; tiles of
 // 128 fall back to 128 x 128 blocks.
-void launch_update(const Tiles &T, const Panel &P, int q, const int32_t *items, int nitems, hipStream_t st)
+void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const int32_t *items, int nitems,
+                   hipStream_t st, bool small)
 {
     if (nitems <= 0) return;
-    const bool big = (T.b % 256) == 0;
+    // "small": a launch beside the running updates (the look-ahead stream)
+    // uses block shapes whose LDS fits in the slot one finished update block
+    // frees; a 1024-thread block with 147 KB of LDS would wait for a whole
+    // idle compute unit.
+    const bool big = (T.b % 256) == 0 && !small;
     switch (q) {
-    case P64: launch_cm<double, 128, 128, 16, 4, 4>(T, P.p64, items, nitems, st); break;
+    case P64: launch_cm<double, 128, 128, 16, 4, 4>(T, P.p64, P2 ? P2->p64 : nullptr, items, nitems, st); break;
     case P32:
-        if (big) launch_cm<float, 256, 128, 16, 4, 2>(T, P.p32, items, nitems, st);
-        else launch_cm<float, 128, 128, 16, 2, 2>(T, P.p32, items, nitems, st);
+        if ((T.b % 256) == 0) launch_cm<float, 256, 128, 16, 4, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
+        else launch_cm<float, 128, 128, 16, 2, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
         break;
-    case P16:
+    case P16: {
+        const uint16_t *p2 = P2 ? P2->p16 : nullptr;
+        const int32_t *s2 = P2 ? P2->pscale : nullptr;
         if (T.lo16 == LO16_BF16) {
-            if (big) launch_rm<RM_BF16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, q, items, nitems, st);
-            else launch_rm<RM_BF16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, q, items, nitems, st);
+            if (big) launch_rm<RM_BF16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
+            else launch_rm<RM_BF16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
         } else {
-            if (big) launch_rm<RM_F16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, q, items, nitems, st);
-            else launch_rm<RM_F16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, q, items, nitems, st);
+            if (big) launch_rm<RM_F16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
+            else launch_rm<RM_F16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
         }
         break;
-    default: launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, P.p8, P.pscale, q, items, nitems, st); break;
+    }
+    default:
+        launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, P.p8, P.pscale, P2 ? P2->p8 : nullptr, P2 ? P2->pscale : nullptr, q,
+                                               items, nitems, st);
+        break;
     }
 }
 

@@ -48,7 +48,10 @@ void launch_zero_upper_diag(const Tiles &T, int k, hipStream_t st);
 void launch_potrf_tile(const Tiles &T, int k, unsigned long long *info, hipStream_t st);
 void launch_trsm_panel(const Tiles &T, const Panel &P, int k, hipStream_t st);
 // grouped update A_IJ -= L_Ik L_Jk^T of class q over `nitems` packed (I << 16 | J) items
-void launch_update(const Tiles &T, const Panel &P, int q, const int32_t *items, int nitems, hipStream_t st);
+// P2 (optional): the next step's panel; the update then covers both steps.
+// small: block shapes that fit beside running update blocks.
+void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const int32_t *items, int nitems,
+                   hipStream_t st, bool small);
 
 // ---- residual (k_residual.hip): items = every lower tile as (I << 16 | J);
 // partial = scratch of nitems * (b/128)^2 doubles; tile_res2 = nt*nt output

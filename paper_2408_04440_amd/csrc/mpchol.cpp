@@ -48,7 +48,7 @@ struct mpchol_handle {
     int src = 0;  // 0 none, 1 matrix, 2 generator
     hipStream_t st2 = nullptr;           // look-ahead stream for the panel of the next step
     hipEvent_t ev_next = nullptr, ev_panel = nullptr;
-    // panel copies, two sets (even / odd steps)
+    // panel copies, four sets (column mod 4: the pair being applied and the pair being factored)
     double *p64 = nullptr;
     float *p32 = nullptr;
     uint16_t *p16 = nullptr;
@@ -67,7 +67,9 @@ struct mpchol_handle {
     double last_eps = 1e-9;
     // schedule
     int32_t *d_items = nullptr;
-    std::vector<int64_t> item_off;  // (nt * 8 + 1) offsets: step, class, part (0: column k+1, 1: the rest)
+    // (npair * 12 + 1) offsets: pair p (columns 2p, 2p+1), class, part
+    // (0: column 2p+1 by column 2p; 1: columns 2p+2, 2p+3 by the pair; 2: the rest by the pair)
+    std::vector<int64_t> item_off;
     uint8_t *d_qmask = nullptr;
     int32_t *d_all_items = nullptr;  // every lower tile, for the residual
     double *d_partial = nullptr, *d_tres2 = nullptr;
@@ -238,12 +240,12 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
         if (rc == MPCHOL_OK && r != MPCHOL_OK) rc = r;
     };
     A(dalloc(&h->slots, h->ntile * h->slot_bytes));
-    A(dalloc(&h->p64, 2 * nt * bb * 8));
-    A(dalloc(&h->p32, 2 * nt * bb * 4));
-    A(dalloc(&h->p16, 2 * nt * bb * 2));
-    A(dalloc(&h->p8, 2 * nt * bb));
-    A(dalloc(&h->pmax, 2 * nt * 8));
-    A(dalloc(&h->pscale, 2 * nt * 4 * 4));
+    A(dalloc(&h->p64, 4 * nt * bb * 8));
+    A(dalloc(&h->p32, 4 * nt * bb * 4));
+    A(dalloc(&h->p16, 4 * nt * bb * 2));
+    A(dalloc(&h->p8, 4 * nt * bb));
+    A(dalloc(&h->pmax, 4 * nt * 8));
+    A(dalloc(&h->pscale, 4 * nt * 4 * 4));
     A(dalloc(&h->d_map, nt * nt));
     A(dalloc(&h->d_tscale, nt * nt * 4));
     A(dalloc(&h->d_fro2, nt * nt * 8));
@@ -412,27 +414,32 @@ static void rule_band(mpchol_handle *h, std::vector<uint8_t> &m)
         }
 }
 
-// Static schedule: for every step k and class q, the update items (I, J),
-// k < J <= I, of that class -- first those of column J = k+1 (which the next
-// step's panel needs), then the rest -- and, per panel tile (I, k), the mask
-// of classes its consumers use.
+// Static schedule, by pairs of steps p (panel columns c = 2p and c+1): per
+// class q, part 0 the tiles of column c+1 (updated by column c alone, on the
+// look-ahead stream inside the pair's panel work), part 1 the tiles of
+// columns c+2 and c+3 (which the next pair's panel needs), part 2 the rest
+// (J >= c+4); parts 1 and 2 take both columns of the pair (K = 2b).  And, per
+// panel tile (I, k), the mask of classes its consumers use.
 static void build_schedule_counts(mpchol_handle *h, std::vector<int32_t> &items, std::vector<uint8_t> &qmask)
 {
-    const int nt = h->nt;
-    h->item_off.assign((size_t)nt * 8 + 1, 0);
+    const int nt = h->nt, npair = (nt + 1) / 2;
+    h->item_off.assign((size_t)npair * 12 + 1, 0);
     items.clear();
-    for (int k = 0; k < nt; ++k)
+    for (int p = 0; p < npair; ++p) {
+        const int c = 2 * p;
         for (int q = 0; q < 4; ++q)
-            for (int part = 0; part < 2; ++part) {
-                h->item_off[((size_t)k * 4 + q) * 2 + part] = (int64_t)items.size();
-                const int jlo = part == 0 ? k + 1 : k + 2, jhi = part == 0 ? k + 1 : nt - 1;
+            for (int part = 0; part < 3; ++part) {
+                h->item_off[((size_t)p * 4 + q) * 3 + part] = (int64_t)items.size();
+                const int jlo = part == 0 ? c + 1 : part == 1 ? c + 2 : c + 4;
+                const int jhi = part == 0 ? c + 1 : part == 1 ? c + 3 : nt - 1;
                 for (int J = jlo; J <= jhi && J < nt; ++J)
                     for (int I = J; I < nt; ++I) {
-                        int c = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
-                        if (c == q) items.push_back((I << 16) | J);
+                        int cl = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
+                        if (cl == q) items.push_back((I << 16) | J);
                     }
             }
-    h->item_off[(size_t)nt * 8] = (int64_t)items.size();
+    }
+    h->item_off[(size_t)npair * 12] = (int64_t)items.size();
     qmask.assign((size_t)nt * nt, 0);
     for (int k = 0; k < nt; ++k)
         for (int I = k + 1; I < nt; ++I) {
@@ -572,11 +579,14 @@ static int panel_step(mpchol_handle *h, const Tiles &T, const Panel &P, int k, h
     return MPCHOL_OK;
 }
 
-static int update_part(mpchol_handle *h, const Tiles &T, const Panel &P, int k, int part, hipStream_t st)
+// The update list (pair p, part) per class on stream st; P2 is the pair's
+// second panel column (null for part 0 or a single-column pair).
+static int update_list(mpchol_handle *h, const Tiles &T, const Panel &P, const Panel *P2, int p, int part,
+                       hipStream_t st)
 {
     const double b3 = (double)h->b * h->b * h->b;
     for (int q = 0; q < 4; ++q) {
-        const size_t o = ((size_t)k * 4 + q) * 2 + part;
+        const size_t o = ((size_t)p * 4 + q) * 3 + part;
         const int64_t off = h->item_off[o];
         const int cnt = (int)(h->item_off[o + 1] - off);
         if (cnt <= 0) continue;
@@ -586,27 +596,45 @@ static int update_part(mpchol_handle *h, const Tiles &T, const Panel &P, int k, 
             HIPCHK(hipEventCreate(&e1));
             HIPCHK(hipEventRecord(e0, st));
         }
-        launch_update(T, P, q, h->d_items + off, cnt, st);
+        launch_update(T, P, P2, q, h->d_items + off, cnt, st, part == 0);
         if (h->o.profile) {
             HIPCHK(hipEventRecord(e1, st));
             h->gev.push_back(e0);
             h->gev.push_back(e1);
             h->gev_class.push_back(q);
-            h->gev_flops.push_back(2.0 * b3 * cnt);
+            h->gev_flops.push_back(2.0 * b3 * cnt * (P2 ? 2 : 1));
         }
     }
     return MPCHOL_OK;
 }
 
-// Right-looking tile algorithm with look-ahead of depth one: the caller's
-// stream A runs the trailing updates; once column k+1 is updated, a second
-// stream B factors tile (k+1,k+1), solves and converts panel k+1 (into the
-// other panel set) while A finishes the rest of step k.
+// Panel work of the pair starting at column c on stream st: POTRF(c,c), TRSM
+// and conversion of column c, the update of column c+1 by column c, then
+// POTRF(c+1,c+1), TRSM and conversion of column c+1.
+static int panel_pair(mpchol_handle *h, const Tiles &T, const Panel *P, int c, hipStream_t st)
+{
+    const int nt = h->nt;
+    launch_potrf_tile(T, c, h->d_info, st);
+    if (c + 1 >= nt) return MPCHOL_OK;
+    int rc = panel_step(h, T, P[c % 4], c, st);
+    if (rc) return rc;
+    rc = update_list(h, T, P[c % 4], nullptr, c / 2, 0, st);
+    if (rc) return rc;
+    launch_potrf_tile(T, c + 1, h->d_info, st);
+    if (c + 2 < nt) rc = panel_step(h, T, P[(c + 1) % 4], c + 1, st);
+    return rc;
+}
+
+// Right-looking tile algorithm taken two steps at a time, with look-ahead:
+// the caller's stream A applies pair (c, c+1) to the trailing tiles with
+// K = 2b; once columns c+2 and c+3 are updated, a second stream B runs the
+// next pair's panel work (into the other two panel sets) while A finishes the
+// rest of the pair's update.
 static int run_factor(mpchol_handle *h, int64_t *info)
 {
     const int nt = h->nt;
     Tiles T = h->tiles();
-    const Panel P[2] = {h->panel(0), h->panel(1)};
+    const Panel P[4] = {h->panel(0), h->panel(1), h->panel(2), h->panel(3)};
     hipStream_t A = h->st, B = h->st2;
     for (auto e : h->gev) (void)hipEventDestroy(e);
     h->gev.clear();
@@ -614,24 +642,18 @@ static int run_factor(mpchol_handle *h, int64_t *info)
     h->gev_flops.clear();
     HIPCHK(hipMemsetAsync(h->d_info, 0xFF, 8, A));
     HIPCHK(hipEventRecord(h->ev[0], A));
-    launch_potrf_tile(T, 0, h->d_info, A);
-    if (nt > 1) {
-        int rc = panel_step(h, T, P[0], 0, A);
-        if (rc) return rc;
-    }
-    for (int k = 0; k + 1 < nt; ++k) {
-        const Panel &Pk = P[k & 1], &Pn = P[(k + 1) & 1];
-        int rc = update_part(h, T, Pk, k, 0, A);
+    int rc = panel_pair(h, T, P, 0, A);
+    if (rc) return rc;
+    for (int c = 0; c + 2 < nt; c += 2) {
+        const Panel &P0 = P[c % 4], *P1 = &P[(c + 1) % 4];
+        rc = update_list(h, T, P0, P1, c / 2, 1, A);
         if (rc) return rc;
         HIPCHK(hipEventRecord(h->ev_next, A));
         HIPCHK(hipStreamWaitEvent(B, h->ev_next, 0));
-        launch_potrf_tile(T, k + 1, h->d_info, B);
-        if (k + 2 < nt) {
-            rc = panel_step(h, T, Pn, k + 1, B);
-            if (rc) return rc;
-        }
+        rc = panel_pair(h, T, P, c + 2, B);
+        if (rc) return rc;
         HIPCHK(hipEventRecord(h->ev_panel, B));
-        rc = update_part(h, T, Pk, k, 1, A);
+        rc = update_list(h, T, P0, P1, c / 2, 2, A);
         if (rc) return rc;
         HIPCHK(hipStreamWaitEvent(A, h->ev_panel, 0));
     }
