@@ -174,12 +174,14 @@ int mpchol_normal_draws(mpchol_t h, int64_t count, uint64_t seed, float *z, uint
  * tile (strict-lower entries of a diagonal tile counted twice).  Synchronizes. */
 int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2);
 
-/* Randomized estimate of the same ratio: with `sets` x 32 probe vectors v
+/* Randomized estimate of the same ratio: with `sets` x 64 probe vectors v
  * (N(0,1) entries from Philox with key derived from `seed`),
  * ||Sigma - L L^T||_F^2 = E ||(Sigma - L L^T) v||^2, and each product costs
- * O(N^2) (Sigma v from the generator or the kept copy, then L (L^T v) with
- * the stored tiles widened to FP64).  Relative standard deviation of the
- * estimate about 1/sqrt(64 sets).  Synchronizes. */
+ * O(N^2) (L (L^T v) with the stored tiles widened to FP64; Sigma v from the
+ * kept copy of set_matrix, or from the generator -- in O(N) per probe by the
+ * exponential kernel's two-sided recursion when its coordinates are
+ * nondecreasing).  Relative standard deviation of the estimate about
+ * 1/sqrt(128 sets).  verify = 2 uses one set.  Synchronizes. */
 int mpchol_backward_error_estimate(mpchol_t h, int32_t sets, uint64_t seed, double *est);
 
 /* Copy the factor's represented values into device L (n x n FP64, ldl >= n;

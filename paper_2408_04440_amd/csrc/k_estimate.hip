@@ -1,16 +1,29 @@
 // Randomized estimate of the backward error ||Sigma - L L^T||_F: for probes
 // V with independent N(0,1) entries, E ||E v||^2 = ||E||_F^2 (E symmetric), and
 // E V = Sigma V - L (L^T V) costs O(N^2 k) instead of the N^3/3 of the exact
-// residual.  Products in FP64 with each stored tile exactly widened; partial
-// sums accumulate with FP64 atomics (the order does not matter for an
-// estimate).  Buffers have NT*b rows, zero beyond n.
+// residual.  Every stored tile is widened exactly to FP64 and read once per
+// product; the products run on the FP64 MFMA.  Buffers have NT*b rows,
+// identity beyond n.
+//
+// Sigma V for the generator with nondecreasing coordinates uses the
+// exponential kernel's separability: with u_j = sigma_j v_j and
+// d_i = exp(-(x_i - x_{i-1})/rho),
+//   F_i = sum_{j<=i} e^{-(x_i-x_j)/rho} u_j = d_i F_{i-1} + u_i,
+//   H_i = sum_{j>=i} e^{-(x_j-x_i)/rho} u_j = d_{i+1} H_{i+1} + u_i,
+//   (Sigma v)_i = sigma_i (F_i + H_i - u_i) + nugget v_i,
+// evaluated as a chunked scan (local recursions, chunk carries, combination).
+// Otherwise (an explicit matrix, or unsorted coordinates) Sigma V is the
+// dense product with Sigma regenerated or read from the kept copy.
 #include "common.h"
+#include "gemm_core.h"
 #include "launch.h"
 
 namespace mpc {
 
-constexpr int EK = 32;   // probes per pass (columns of V)
-constexpr int EB = 64;   // rows / columns of a staged sub-block
+constexpr int EK = 64;   // probes per pass (columns of V)
+constexpr int EB = 64;   // rows / columns of an output block
+constexpr int ER = 32;   // K rows staged per step
+constexpr int SC = 256;  // rows per scan chunk
 
 __device__ inline double source_ij(const Tiles &T, const Source &S, int64_t i, int64_t j)
 {
@@ -25,20 +38,23 @@ __device__ inline double source_ij(const Tiles &T, const Source &S, int64_t i, i
     return v;
 }
 
-// SV[i, q] += sum_{j in chunk} Sigma_ij V[j, q]; one thread per row i, 256 rows
-// x 16384 columns per block, V staged 128 rows at a time.
+// ---------------------------------------------------------------- dense Sigma V
+// SV[i, q0+q] += sum_{j in chunk} Sigma_ij V[j, q0+q] for 32 probes; one
+// thread per row i, 256 rows x 16384 columns per block, V staged 128 rows at
+// a time.
+constexpr int DQ = 32;
 __global__ __launch_bounds__(256) void sigma_v_kernel(Tiles T, Source S, const double *V, int64_t ldv, double *SV)
 {
-    __shared__ double vs[128][EK + 1];
+    __shared__ double vs[128][DQ + 1];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.y * 16384;
     const int64_t np = (int64_t)T.nt * T.b;
-    double acc[EK];
+    double acc[DQ];
 #pragma unroll
-    for (int q = 0; q < EK; ++q) acc[q] = 0.0;
+    for (int q = 0; q < DQ; ++q) acc[q] = 0.0;
     for (int64_t jc = j0; jc < j0 + 16384 && jc < np; jc += 128) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 128 * EK; e += 256) {
+        for (int e = threadIdx.x; e < 128 * DQ; e += 256) {
             int jj = e % 128, q = e / 128;
             vs[jj][q] = (jc + jj < np) ? V[jc + jj + q * ldv] : 0.0;
         }
@@ -47,87 +63,205 @@ __global__ __launch_bounds__(256) void sigma_v_kernel(Tiles T, Source S, const d
             for (int jj = 0; jj < 128 && jc + jj < np; ++jj) {
                 double s = source_ij(T, S, i, jc + jj);
 #pragma unroll
-                for (int q = 0; q < EK; ++q) acc[q] += s * vs[jj][q];
+                for (int q = 0; q < DQ; ++q) acc[q] += s * vs[jj][q];
             }
         }
     }
     if (i < np)
 #pragma unroll
-        for (int q = 0; q < EK; ++q) atomicAdd(SV + i + q * ldv, acc[q]);
+        for (int q = 0; q < DQ; ++q) atomicAdd(SV + i + q * ldv, acc[q]);
 }
 
-// Z[rows of I] = sum_{K <= I} L_IK W[rows of K] for one 64-row strip of tile row I.
-__global__ __launch_bounds__(256) void l_apply_kernel(Tiles T, const double *W, int64_t ldw, double *Z)
+// ---------------------------------------------------------------- scan Sigma V
+// Local recursions of chunk c for probe q (rows s .. e, e < n):
+//   f_i = d_i f_{i-1} + u_i (f_{s-1} = 0)   -> F buffer,
+//   h_i = d_{i+1} h_{i+1} + u_i (h_{e+1} = 0) -> H buffer.
+__global__ __launch_bounds__(64) void scan_local_kernel(Tiles T, Source S, const double *V, int64_t ldv, double *F,
+                                                        double *H)
 {
-    __shared__ double ls[EB][EB + 1];  // ls[c][r]
-    __shared__ double ws[EB][EK + 1];
-    const int b = T.b, per = b / EB;
-    const int I = blockIdx.x / per, r0 = (blockIdx.x % per) * EB;
-    const int r = threadIdx.x & 63, g = threadIdx.x >> 6;  // 4 groups of 8 probes
-    double acc[EK / 4];
-#pragma unroll
-    for (int q = 0; q < EK / 4; ++q) acc[q] = 0.0;
-    for (int K = 0; K <= I; ++K) {
-        const int cls = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
-        const int ts = T.tscale[I + (int64_t)K * T.nt];
-        const char *tile = T.slots + tile_index(I, K) * T.slot_bytes;
-        for (int c0 = 0; c0 < b; c0 += EB) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < EB * EB; e += 256) {
-                int rr = e % EB, cc = e / EB;
-                ls[cc][rr] = load_stored(tile, cls, T.lo16, ts, (int64_t)(r0 + rr) + (int64_t)(c0 + cc) * b);
-            }
-            for (int e = threadIdx.x; e < EB * EK; e += 256) {
-                int cc = e % EB, q = e / EB;
-                ws[cc][q] = W[(int64_t)K * b + c0 + cc + q * ldw];
-            }
-            __syncthreads();
-            for (int cc = 0; cc < EB; ++cc) {
-                double l = ls[cc][r];
-#pragma unroll
-                for (int q = 0; q < EK / 4; ++q) acc[q] += l * ws[cc][g * (EK / 4) + q];
-            }
-        }
+    const int c = blockIdx.x, q = threadIdx.x;
+    const int64_t s = (int64_t)c * SC, e = min((int64_t)T.n, s + SC) - 1;
+    const double *v = V + q * ldv;
+    double f = 0.0;
+    for (int64_t i = s; i <= e; ++i) {
+        const double d = (i > s) ? exp(-(S.x[i] - S.x[i - 1]) / S.rho) : 0.0;
+        f = d * f + S.sigma[i] * v[i];
+        F[i + q * ldv] = f;
     }
-#pragma unroll
-    for (int q = 0; q < EK / 4; ++q) Z[(int64_t)I * b + r0 + r + (g * (EK / 4) + q) * ldw] = acc[q];
+    double h = 0.0;
+    for (int64_t i = e; i >= s; --i) {
+        const double d = (i < e) ? exp(-(S.x[i + 1] - S.x[i]) / S.rho) : 0.0;
+        h = d * h + S.sigma[i] * v[i];
+        H[i + q * ldv] = h;
+    }
 }
 
-// W[rows of K] = sum_{I >= K} L_IK^T V[rows of I] for one 64-column strip of tile column K.
+// Chunk carries for probe q: Fin[c] = F_{s_c - 1}, Hin[c] = H_{e_c + 1} (0
+// at the ends), from the chunk-boundary values of the local recursions.
+__global__ __launch_bounds__(64) void scan_carry_kernel(Tiles T, Source S, const double *F, const double *H,
+                                                        int64_t ldv, int nchunk, double *Fin, double *Hin)
+{
+    const int q = threadIdx.x;
+    double carry = 0.0;  // F at the last row of the previous chunk
+    for (int c = 0; c < nchunk; ++c) {
+        const int64_t s = (int64_t)c * SC, e = min((int64_t)T.n, s + SC) - 1;
+        Fin[c * EK + q] = carry;
+        const double dc = (c > 0) ? exp(-(S.x[e] - S.x[s - 1]) / S.rho) : 0.0;
+        carry = F[e + q * ldv] + dc * carry;
+    }
+    carry = 0.0;  // H at the first row of the next chunk
+    for (int c = nchunk - 1; c >= 0; --c) {
+        const int64_t s = (int64_t)c * SC, e = min((int64_t)T.n, s + SC) - 1;
+        Hin[c * EK + q] = carry;
+        const double dc = (c < nchunk - 1) ? exp(-(S.x[e + 1] - S.x[s]) / S.rho) : 0.0;
+        carry = H[s + q * ldv] + dc * carry;
+    }
+}
+
+// SV_i = sigma_i (F_i + H_i - u_i) + nugget v_i with the carries applied;
+// rows >= n are the identity's.  F may alias SV (each element read, then written).
+__global__ __launch_bounds__(256) void scan_finish_kernel(Tiles T, Source S, const double *V, int64_t ldv,
+                                                          const double *F, const double *H, const double *Fin,
+                                                          const double *Hin, double *SV)
+{
+    const int64_t np = (int64_t)T.nt * T.b;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= np * EK) return;
+    const int64_t i = e % np;
+    const int q = (int)(e / np);
+    const double v = V[i + q * ldv];
+    if (i >= T.n) {
+        SV[i + q * ldv] = v;
+        return;
+    }
+    const int c = (int)(i / SC);
+    const int64_t s = (int64_t)c * SC, ce = min((int64_t)T.n, s + SC) - 1;
+    double Fi = F[i + q * ldv], Hi = H[i + q * ldv];
+    if (c > 0) Fi += exp(-(S.x[i] - S.x[s - 1]) / S.rho) * Fin[c * EK + q];
+    if (ce + 1 < T.n) Hi += exp(-(S.x[ce + 1] - S.x[i]) / S.rho) * Hin[c * EK + q];
+    const double u = S.sigma[i] * v;
+    SV[i + q * ldv] = S.sigma[i] * (Fi + Hi - u) + S.nugget * v;
+}
+
+// ---------------------------------------------------------------- L^T V, L W
+// Stage an ER x EB (rows x columns) piece of stored tile (cls, ts) at
+// (r0, c0) into st[r][c], widened to FP64.
+__device__ inline void stage_tile(const char *tile, int cls, int lo16, int ts, int b, int r0, int c0,
+                                  double (*st)[EB + 1])
+{
+    for (int e = threadIdx.x; e < ER * EB; e += 256) {
+        const int r = e % ER, c = e / ER;
+        st[r][c] = load_stored(tile, cls, lo16, ts, (int64_t)(r0 + r) + (int64_t)(c0 + c) * b);
+    }
+}
+
+// W[rows c0.. of tile column K] = sum_{I >= K} L_IK(:, c0:c0+64)^T V[rows of I]:
+// block per (K, 64-column strip), four waves of 32 x 32 outputs (c x probe),
+// K dimension = the rows r of L_IK, ER at a time.
 __global__ __launch_bounds__(256) void lt_apply_kernel(Tiles T, const double *V, int64_t ldv, double *W)
 {
-    __shared__ double ls[EB][EB + 1];  // ls[c][r]
-    __shared__ double vs[EB][EK + 1];
+    __shared__ double ls[ER][EB + 1];  // ls[r][c] = L_IK(r0 + r, c0 + c)
+    __shared__ double vs[ER][EK + 1];  // vs[r][q] = V[I*b + r0 + r, q]
     const int b = T.b, per = b / EB;
     const int K = blockIdx.x / per, c0 = (blockIdx.x % per) * EB;
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    double acc[EK / 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % 2, wn = wave / 2, gi = lane & 15, gg = lane >> 4;
+    double4_t acc[2][2];
 #pragma unroll
-    for (int q = 0; q < EK / 4; ++q) acc[q] = 0.0;
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
     for (int I = K; I < T.nt; ++I) {
         const int cls = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
         const int ts = T.tscale[I + (int64_t)K * T.nt];
         const char *tile = T.slots + tile_index(I, K) * T.slot_bytes;
-        for (int r0 = 0; r0 < b; r0 += EB) {
+        for (int r0 = 0; r0 < b; r0 += ER) {
             __syncthreads();
-            for (int e = threadIdx.x; e < EB * EB; e += 256) {
-                int rr = e % EB, cc = e / EB;
-                ls[cc][rr] = load_stored(tile, cls, T.lo16, ts, (int64_t)(r0 + rr) + (int64_t)(c0 + cc) * b);
-            }
-            for (int e = threadIdx.x; e < EB * EK; e += 256) {
-                int rr = e % EB, q = e / EB;
-                vs[rr][q] = V[(int64_t)I * b + r0 + rr + q * ldv];
+            stage_tile(tile, cls, T.lo16, ts, b, r0, c0, ls);
+            for (int e = tid; e < ER * EK; e += 256) {
+                const int r = e % ER, q = e / ER;
+                vs[r][q] = V[(int64_t)I * b + r0 + r + q * ldv];
             }
             __syncthreads();
-            for (int rr = 0; rr < EB; ++rr) {
-                double l = ls[c][rr];
 #pragma unroll
-                for (int q = 0; q < EK / 4; ++q) acc[q] += l * vs[rr][g * (EK / 4) + q];
+            for (int s = 0; s < ER / 4; ++s) {
+                double fa[2], fb[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) fa[m] = ls[s * 4 + gg][wm * 32 + m * 16 + gi];
+#pragma unroll
+                for (int n = 0; n < 2; ++n) fb[n] = vs[s * 4 + gg][wn * 32 + n * 16 + gi];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[n], fa[m], acc[m][n], 0, 0, 0);
+            }
+        }
+    }
+    // swapped operands: lane gi owns output row c, element v probe acc_row(gg, v)
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = wm * 32 + m * 16 + gi, q = wn * 32 + n * 16 + acc_row<double>(gg, v);
+                W[(int64_t)K * b + c0 + c + q * ldv] = acc[m][n][v];
+            }
+}
+
+// Z[rows r0.. of tile row I] = sum_{K <= I} L_IK(r0:r0+64, :) W[rows of K]:
+// block per (I, 64-row strip), K dimension = the columns of L_IK, ER at a time.
+__global__ __launch_bounds__(256) void l_apply_kernel(Tiles T, const double *W, int64_t ldw, double *Z)
+{
+    __shared__ double ls[ER][EB + 1];  // ls[c][r] = L_IK(r0 + r, c0 + c)
+    __shared__ double ws[ER][EK + 1];  // ws[c][q] = W[K*b + c0 + c, q]
+    const int b = T.b, per = b / EB;
+    const int I = blockIdx.x / per, r0 = (blockIdx.x % per) * EB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % 2, wn = wave / 2, gi = lane & 15, gg = lane >> 4;
+    double4_t acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int K = 0; K <= I; ++K) {
+        const int cls = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
+        const int ts = T.tscale[I + (int64_t)K * T.nt];
+        const char *tile = T.slots + tile_index(I, K) * T.slot_bytes;
+        for (int c0 = 0; c0 < b; c0 += ER) {
+            __syncthreads();
+            for (int e = tid; e < ER * EB; e += 256) {
+                const int r = e % EB, c = e / EB;
+                ls[c][r] = load_stored(tile, cls, T.lo16, ts, (int64_t)(r0 + r) + (int64_t)(c0 + c) * b);
+            }
+            for (int e = tid; e < ER * EK; e += 256) {
+                const int c = e % ER, q = e / ER;
+                ws[c][q] = W[(int64_t)K * b + c0 + c + q * ldw];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < ER / 4; ++s) {
+                double fa[2], fb[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) fa[m] = ls[s * 4 + gg][wm * 32 + m * 16 + gi];
+#pragma unroll
+                for (int n = 0; n < 2; ++n) fb[n] = ws[s * 4 + gg][wn * 32 + n * 16 + gi];
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[n], fa[m], acc[m][n], 0, 0, 0);
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < EK / 4; ++q) W[(int64_t)K * b + c0 + c + (g * (EK / 4) + q) * ldv] = acc[q];
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wm * 32 + m * 16 + gi, q = wn * 32 + n * 16 + acc_row<double>(gg, v);
+                Z[(int64_t)I * b + r0 + r + q * ldw] = acc[m][n][v];
+            }
 }
 
 // Widen FP32 normals to FP64 probes, zero beyond n.
@@ -161,17 +295,30 @@ __global__ __launch_bounds__(1024) void residual_norm_kernel(const double *SV, c
     if (threadIdx.x == 0) *out = s[0];
 }
 
-// scratch: 3 * NT*b*EK doubles + n*EK floats.  Writes sum ||E v_q||^2 over
-// the EK probes to *out (device).
-void launch_estimate(const Tiles &T, const Source &S, uint64_t seed, double *scratch, float *zbuf, double *out,
-                     hipStream_t st)
+int estimate_chunks(int64_t n) { return (int)((n + SC - 1) / SC); }
+
+// scratch: 3 * NT*b*EK doubles + 2 * chunks*EK doubles; zbuf: n*EK floats.
+// Writes sum ||E v_q||^2 over the EK probes to *out (device).  sorted: the
+// generator's coordinates are nondecreasing (scan path for Sigma V).
+void launch_estimate(const Tiles &T, const Source &S, bool sorted, uint64_t seed, double *scratch, float *zbuf,
+                     double *out, hipStream_t st)
 {
     const int64_t np = (int64_t)T.nt * T.b;
     double *V = scratch, *SV = scratch + np * EK, *W = scratch + 2 * np * EK, *Z = scratch;  // Z reuses V
+    double *Fin = scratch + 3 * np * EK, *Hin = Fin + (int64_t)estimate_chunks(T.n) * EK;
     launch_normal_matrix(seed, T.n, EK, zbuf, T.n, st);
-    probes_kernel<<<(unsigned)((np * EK + 255) / 256), 256, 0, st>>>(zbuf, T.n, np, V);
-    (void)hipMemsetAsync(SV, 0, (size_t)np * EK * 8, st);
-    sigma_v_kernel<<<dim3((unsigned)((np + 255) / 256), (unsigned)((np + 16383) / 16384)), 256, 0, st>>>(T, S, V, np, SV);
+    const unsigned eb = (unsigned)((np * EK + 255) / 256);
+    probes_kernel<<<eb, 256, 0, st>>>(zbuf, T.n, np, V);
+    if (sorted && !S.orig) {
+        const int nc = estimate_chunks(T.n);
+        scan_local_kernel<<<nc, EK, 0, st>>>(T, S, V, np, SV, W);  // F -> SV, H -> W
+        scan_carry_kernel<<<1, EK, 0, st>>>(T, S, SV, W, np, nc, Fin, Hin);
+        scan_finish_kernel<<<eb, 256, 0, st>>>(T, S, V, np, SV, W, Fin, Hin, SV);
+    } else {
+        (void)hipMemsetAsync(SV, 0, (size_t)np * EK * 8, st);
+        const dim3 g((unsigned)((np + 255) / 256), (unsigned)((np + 16383) / 16384));
+        for (int q0 = 0; q0 < EK; q0 += DQ) sigma_v_kernel<<<g, 256, 0, st>>>(T, S, V + q0 * np, np, SV + q0 * np);
+    }
     const int per = T.b / EB;
     lt_apply_kernel<<<(unsigned)((int64_t)T.nt * per), 256, 0, st>>>(T, V, np, W);
     l_apply_kernel<<<(unsigned)((int64_t)T.nt * per), 256, 0, st>>>(T, W, np, Z);

@@ -60,8 +60,9 @@ void launch_residual_items(const Tiles &T, const Source &S, const int32_t *items
 
 // ---- backward-error estimate (k_estimate.hip): scratch 3*nt*b*probes doubles,
 // zbuf n*probes floats; *out = sum over the probes of ||(Sigma - L L^T) v||^2
-void launch_estimate(const Tiles &T, const Source &S, uint64_t seed, double *scratch, float *zbuf, double *out,
-                     hipStream_t st);
+void launch_estimate(const Tiles &T, const Source &S, bool sorted, uint64_t seed, double *scratch, float *zbuf,
+                     double *out, hipStream_t st);
+int estimate_chunks(int64_t n);
 int estimate_probes();
 
 // ---- solve, sample (k_apply.hip)

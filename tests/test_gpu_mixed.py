@@ -189,13 +189,19 @@ def test_full_size_fp8_129600(orc):
     assert abs(ld - ref) / abs(ref) <= 1e-8
 
 
-@pytest.mark.parametrize("L,tile,eps", [(32, 128, 1e-6), (32, 128, 1e-4), (48, 256, 1e-5), (30, 128, 1e-9)])
-def test_backward_error_estimate(L, tile, eps):
-    """The randomized estimate (64 probes) against the exact FP64 residual:
-    its relative standard deviation is about 1/sqrt(2*64) = 0.09, so within
-    4 sigma of the exact value."""
+@pytest.mark.parametrize("L,tile,eps,shuffle", [(32, 128, 1e-6, False), (32, 128, 1e-4, False), (48, 256, 1e-5, False),
+                                               (30, 128, 1e-9, False), (32, 128, 1e-6, True), (40, 256, 1e-5, True)])
+def test_backward_error_estimate(L, tile, eps, shuffle):
+    """The randomized estimate (one set of 64 probes) against the exact FP64
+    residual: its relative standard deviation is about 1/sqrt(2*64) = 0.09, so
+    within 4 sigma of the exact value.  With the coordinates in their natural
+    (increasing) order Sigma v comes from the exponential kernel's two-sided
+    recursion; shuffled coordinates take the dense product."""
     n = L * L
     sigma, x = synth.workload(L)
+    if shuffle:
+        perm = np.argsort(synth.uniform01(41, n))
+        sigma, x = sigma[perm], x[perm]
     mod = M()
     h = mod.mpchol_create(n, tile)
     try:
@@ -203,11 +209,13 @@ def test_backward_error_estimate(L, tile, eps):
         mod.mpchol_precision_map(h, mod.RULE_NORM, eps)
         assert mod.mpchol_factor(h) == 0
         be = mod.mpchol_backward_error(h)
-        est = mod.mpchol_backward_error_estimate(h, 2, 11)
+        est = mod.mpchol_backward_error_estimate(h, 1, 11)
+        est2 = mod.mpchol_backward_error_estimate(h, 2, 11)
     finally:
         mod.mpchol_destroy(h)
-    log(f"  estimate n={n} eps={eps}: exact={be:.3e} estimate={est:.3e}")
+    log(f"  estimate n={n} eps={eps} shuffle={shuffle}: exact={be:.3e} estimate={est:.3e} (2 sets {est2:.3e})")
     assert abs(est / be - 1.0) <= 4.0 / np.sqrt(2.0 * 64)
+    assert abs(est2 / be - 1.0) <= 4.0 / np.sqrt(2.0 * 128)
 
 
 def test_verify_with_estimator_falls_back():
