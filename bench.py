@@ -63,6 +63,19 @@ def update_kernel_hash():
     return h.hexdigest()[:16]
 
 
+def solve_backward_error(sigma, x, rho, nugget, X, B0, fro):
+    """Normwise backward error ||B - Sigma X||_F / (||Sigma||_F ||X||_F + ||B||_F)
+    of the solve, with Sigma regenerated on the host in row blocks."""
+    n = len(sigma)
+    R = np.array(B0, dtype=np.float64, copy=True)
+    for i0 in range(0, n, 2048):
+        i1 = min(n, i0 + 2048)
+        S = sigma[i0:i1, None] * sigma[None, :] * np.exp(-np.abs(x[i0:i1, None] - x[None, :]) / rho)
+        S[np.arange(i1 - i0), np.arange(i0, i1)] += nugget
+        R[i0:i1] -= S @ X
+    return float(np.linalg.norm(R) / (fro * np.linalg.norm(X) + np.linalg.norm(B0)))
+
+
 def verify_value(v):
     """The first verified map's backward error for the JSON line: None when no
     map was verified, "breakdown" when its factorization failed."""
@@ -121,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
     ap.add_argument("--eps", type=float, default=None, help="override the workload's accuracy threshold")
+    ap.add_argument("--band-variant", type=int, default=None, choices=[1, 2, 3],
+                    help="band rule variant: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP")
     ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
                     help="precision map of the timed steps (default: norm, or fp64 for FP64-only workloads)")
     ap.add_argument("--compare", default=None, help="comma list of extra rules timed once after the steps, "
@@ -165,8 +180,9 @@ def main():
              "learned_unverified": M.RULE_LEARNED}
     stream = torch.cuda.current_stream()
     need_w = (args.rule or "").startswith("learned") or "learned" in args.compare
+    extra = {} if args.band_variant is None else {"band_variant": args.band_variant}
     h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
-                        verify=2 if need_w else 0, verify_eps=eps)
+                        verify=2 if need_w else 0, verify_eps=eps, **extra)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
     if need_w:
         from paper_2408_04440_amd import selector as S
@@ -217,6 +233,11 @@ def main():
     hist = np.bincount(cmap[np.tril_indices(nt, -1)], minlength=4)
 
     # accuracy of the mixed factor of the last step
+    solve_be = None
+    if B is not None:
+        X = B.cpu().numpy().T  # n x rhs, the last step's solution
+        solve_be = solve_backward_error(sigma, x, rho, nugget, X, synth.rhs(n, cfg["rhs"]), st["total_fro"])
+        log(f"  solve backward error {solve_be:.3e}")
     berr = None
     if not args.no_berr:
         berr = M.mpchol_backward_error(h)
@@ -294,6 +315,7 @@ def main():
         "compare": compare or None,
         "backward_error": berr,
         "logdet_rel_err": None if ld_ref is None else abs(ld - ld_ref) / abs(ld_ref),
+        "solve_backward_error": solve_be,
         "tiles_per_class": {CLASS[c]: int(hist[c]) for c in range(4)},
         "flop_share": {CLASS[c]: round(st["flops_per_class"][c] / sum(st["flops_per_class"]), 4) for c in range(4)},
         "gemm_tflops": {CLASS[c]: round(st["gemm_flops"][c] / st["t_gemm_ms"][c] / 1e9, 2)

@@ -58,3 +58,24 @@ def test_synth_layout():
     u = synth.uniform01(0, 100000)
     assert u.min() > 0 and u.max() <= 1 and abs(u.mean() - 0.5) < 0.01
     assert np.array_equal(synth.splitmix64(5, 4), synth.splitmix64(5, 4))
+
+
+def test_bench_solve_backward_error():
+    """The bench's solve check: ~1e-16 for a numpy solve of the same Sigma,
+    exactly 1 for X = 0, and independent of the row blocking."""
+    import bench
+    import synth
+
+    sigma, x = synth.workload(48)  # n = 2304, two row blocks
+    n = len(sigma)
+    S = sigma[:, None] * sigma[None, :] * np.exp(-np.abs(x[:, None] - x[None, :]) / 5.0) + 1e-8 * np.eye(n)
+    B = synth.rhs(n, 3)
+    X = np.linalg.solve(S, B)
+    fro = np.linalg.norm(S)
+    be = bench.solve_backward_error(sigma, x, 5.0, 1e-8, X, B, fro)
+    assert be < 1e-14
+    assert bench.solve_backward_error(sigma, x, 5.0, 1e-8, np.zeros_like(B), B, fro) == 1.0
+    R = B - S @ (X * (1 + 1e-6))
+    want = np.linalg.norm(R) / (fro * np.linalg.norm(X * (1 + 1e-6)) + np.linalg.norm(B))
+    got = bench.solve_backward_error(sigma, x, 5.0, 1e-8, X * (1 + 1e-6), B, fro)
+    assert abs(got - want) <= 1e-6 * want
