@@ -56,6 +56,7 @@ def lib():
         L.orc_cov_entry.restype = d
         L.orc_cov_entry.argtypes = [dp, dp, d, d, i64, i64]
         L.orc_cov_dense.argtypes = [i64, dp, dp, d, d, dp, i64]
+        L.orc_cov_samples.argtypes = [i64, i64, dp, i64, d, d, dp, i64]
         L.orc_threads.restype = i32
         L.orc_potrf.restype = i64
         L.orc_potrf.argtypes = [i64, dp, i64]
@@ -115,6 +116,17 @@ def cov_dense(sigma, x, rho, nugget):
     A = np.empty((n, n), order="F")
     lib().orc_cov_dense(n, _dp(sigma), _dp(x), rho, nugget, _dp(A), n)
     return A
+
+
+def cov_samples(xi, scale, nugget):
+    """S = scale * xi xi^T + nugget I for samples xi (n x m): the covariance
+    estimator of the residual vectors (Sec. III, constructing the covariance
+    matrix)."""
+    xi = _fortran(xi)
+    n, m = xi.shape
+    S = np.empty((n, n), order="F")
+    lib().orc_cov_samples(n, m, _dp(xi), n, float(scale), float(nugget), _dp(S), n)
+    return S
 
 
 def cov_entry(sigma, x, rho, nugget, i, j):

@@ -55,6 +55,32 @@ void orc_cov_dense(int64_t n, const double *sigma, const double *x, double rho, 
 }
 
 /* ------------------------------------------------------------------------
+ * Covariance from samples (the estimator of the residual covariance in Sec.
+ * III, "Modeling the Temporal Dependence and Constructing a Covariance
+ * Matrix": the average of the outer products of the R(T-P) residual vectors,
+ * plus a small diagonal perturbation when there are fewer samples than L^2):
+ *   S_ij = scale * sum_k xi_ik xi_jk + nugget * delta_ij,
+ * xi column-major n x m (leading dimension ldxi), terms summed in k order,
+ * S full (both triangles) column-major.
+ * Pinned by: xi = [I 0] (S = (scale + nugget) I), a rank-one xi (closed
+ * form), and xi = L0 H with a Sylvester-Hadamard H (H H^T = m I): with
+ * scale = 1/m, S = L0 L0^T exactly.
+ * ---------------------------------------------------------------------- */
+void orc_cov_samples(int64_t n, int64_t m, const double *xi, int64_t ldxi, double scale, double nugget, double *S,
+                     int64_t lds)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = j; i < n; ++i) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < m; ++k) acc += xi[i + k * ldxi] * xi[j + k * ldxi];
+            double v = scale * acc + ((i == j) ? nugget : 0.0);
+            S[i + j * lds] = v;
+            S[j + i * lds] = v;
+        }
+}
+
+/* ------------------------------------------------------------------------
  * O1: exact FP64 Cholesky, A = L L^T with L lower and positive diagonal
  * (the factorization of Sec. III.A.3).  Right-looking, one column at a time:
  *   L_kk = sqrt(A_kk); L_ik = A_ik / L_kk; A_ij -= L_ik L_jk (i >= j > k).

@@ -33,6 +33,7 @@ SEED_SIGMA = 0
 SEED_RHS = 1
 SEED_DRAWS = 2
 SEED_MLP_INIT = 3
+SEED_SAMPLES = 4
 
 
 def splitmix64(seed: int, count: int) -> np.ndarray:
@@ -116,6 +117,24 @@ def int_lower(n: int, seed: int, lo: int = -3, hi: int = 3, diag_lo: int = 1, di
     L0 = np.tril(off, -1).astype(np.float64)
     L0[np.arange(n), np.arange(n)] = d
     return L0
+
+
+def hadamard(m: int) -> np.ndarray:
+    """Sylvester-Hadamard matrix of order m (a power of two): entries +-1,
+    H H^T = m I."""
+    assert m >= 1 and (m & (m - 1)) == 0
+    H = np.ones((1, 1))
+    while H.shape[0] < m:
+        H = np.block([[H, H], [H, -H]])
+    return H
+
+
+def samples(n: int, m: int, seed: int = SEED_SAMPLES) -> np.ndarray:
+    """Residual-like samples for the covariance producer: column-major n x m,
+    N(0,1) entries scaled by the SH spectrum (1+l)^-1 of coefficient i."""
+    l = sh_degrees(int(np.ceil(np.sqrt(n))))[:n]
+    z = normal(seed, n * m).reshape(m, n).T
+    return np.asfortranarray(z / (1.0 + l)[:, None])
 
 
 def features_toy(count: int, seed: int) -> tuple[np.ndarray, np.ndarray]:

@@ -430,3 +430,42 @@ def test_mlp_training_decreases_loss(orc):
     assert l1 < 0.3 * l0
     acc = np.mean(np.argmax(orc.mlp_forward(P, X), axis=1) == y)
     assert acc > 0.9
+
+
+# ---------------------------------------------------------------- covariance from samples
+def test_cov_samples_identity_samples(orc):
+    """xi = [I 0]: S = (scale + nugget) I exactly (drops of the scale, the
+    nugget or a transposed contraction all fail)."""
+    n, m = 7, 12
+    xi = np.zeros((n, m))
+    xi[:, :n] = np.eye(n)
+    S = orc.cov_samples(xi, 0.25, 0.125)
+    assert S.shape == (n, n)
+    assert np.array_equal(S, 0.375 * np.eye(n))
+
+
+def test_cov_samples_rank_one_closed_form(orc):
+    """xi = u v^T: S = scale |v|^2 u u^T + nugget I."""
+    u = synth.normal(5, 9)
+    v = synth.normal(6, 13)
+    S = orc.cov_samples(np.outer(u, v), 0.5, 1e-3)
+    want = 0.5 * float(v @ v) * np.outer(u, u) + 1e-3 * np.eye(9)
+    assert np.max(np.abs(S - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+def test_cov_samples_hadamard_gives_exact_covariance(orc):
+    """xi = L0 H_n with H_n the first n rows of a Sylvester-Hadamard matrix of
+    order m (H_n H_n^T = m I): with scale 1/m the estimator returns L0 L0^T
+    exactly, the population covariance the samples were drawn to have."""
+    n, m = 24, 32
+    L0 = synth.int_lower(n, 9)
+    xi = L0 @ synth.hadamard(m)[:n, :]
+    S = orc.cov_samples(xi, 1.0 / m, 0.0)
+    assert np.array_equal(S, L0 @ L0.T)
+
+
+def test_cov_samples_symmetric_psd(orc):
+    xi = synth.samples(40, 25)
+    S = orc.cov_samples(xi, 1.0 / 25, 1e-6)
+    assert np.array_equal(S, S.T)
+    assert np.linalg.eigvalsh(S).min() >= 1e-6 * (1 - 1e-6)
