@@ -140,6 +140,8 @@ def main():
                     help="precision map of the timed steps (default: norm, or fp64 for FP64-only workloads)")
     ap.add_argument("--compare", default=None, help="comma list of extra rules timed once after the steps, "
                     "each with its backward error (e.g. norm,learned)")
+    ap.add_argument("--producer", type=int, default=0, metavar="M",
+                    help="also time the covariance producer (Sigma = Xi Xi^T / M + nugget I) for M samples")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB megabytes first (counter calibration)")
     args = ap.parse_args()
@@ -286,6 +288,25 @@ def main():
                          "verify_first": verify_value(stc["verify_first"]),
                          "tiles_per_class": [int(v) for v in stc["tiles_per_class"]]}
         log(f"  compare {name}: {compare[name]}")
+    producer = None
+    if args.producer > 0:
+        # residual-like samples on the device: N(0,1) scaled by (1+l)^-1, seed 4
+        m_s = args.producer
+        g = torch.Generator(device="cuda")
+        g.manual_seed(synth.SEED_SAMPLES)
+        Xs = torch.randn((m_s, n), dtype=torch.float64, device="cuda", generator=g)
+        Xs *= torch.tensor(1.0 / (1.0 + synth.sh_degrees(L)[:n]), device="cuda")
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        M.mpchol_set_samples(h, Xs.T, 1.0 / m_s, nugget)
+        t_wall = (time.perf_counter() - tp0) * 1e3
+        stp = M.mpchol_get_stats(h)
+        fl = float(n) * (n + 1) * m_s
+        producer = {"m": m_s, "t_ms": round(stp["t_samples_ms"], 2), "t_call_ms": round(t_wall, 2),
+                    "tflops": round(fl / stp["t_samples_ms"] / 1e9, 3), "fp64_peak_frac": round(fl / stp["t_samples_ms"] / 1e9 / PEAK[0], 4),
+                    "algorithmic_flops": fl}
+        log(f"  producer: {producer}")
+        del Xs
     M.mpchol_destroy(h)
 
     cpu, ld_ref = (None, None)
@@ -313,6 +334,7 @@ def main():
         "fallbacks": st["fallbacks"],
         "verify_first": verify_value(st["verify_first"]),
         "compare": compare or None,
+        "producer": producer,
         "backward_error": berr,
         "logdet_rel_err": None if ld_ref is None else abs(ld - ld_ref) / abs(ld_ref),
         "solve_backward_error": solve_be,

@@ -98,6 +98,7 @@ typedef struct mpchol_stats {
     int32_t rule_used;           /* rule of the map the last factor ran with */
     double verify_first;         /* backward error (exact or estimated) of the first map verify judged;
                                     +inf if that map's factorization broke down; -1 if no map was verified */
+    double t_samples_ms;         /* last set_samples: the covariance product (ms) */
 } mpchol_stats;
 
 /* Default options: device 0, null stream, FP16, band 1, all classes allowed. */
@@ -125,6 +126,22 @@ int mpchol_set_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_devic
  * diagonal perturbation that keeps it positive definite (Sec. III.A.3).
  * sigma and x: host arrays of n doubles; rho > 0; nugget >= 0. */
 int mpchol_set_generator(mpchol_t h, const double *sigma, const double *x, double rho, double nugget);
+
+/* Use the covariance estimated from samples (Sec. III, "Modeling the Temporal
+ * Dependence and Constructing a Covariance Matrix": the average of the outer
+ * products of the R(T-P) residual vectors, with a small diagonal perturbation
+ * when there are fewer samples than L^2):
+ *   Sigma = scale * Xi Xi^T + nugget * I,
+ * Xi the n x m samples, column-major with leading dimension ldxi >= n, in
+ * host memory (or device memory if on_device); e.g. scale = 1/(R(T-P)).
+ * Computed on the GPU by a tall-skinny FP64 MFMA SYRK into the kept FP64
+ * copy, which maps, factor and residuals then read as after set_matrix.  The
+ * caller keeps ownership of Xi.  Temporary device memory: (NT*b) x
+ * roundup(m, 16) doubles, plus n x m for host input.  Synchronizes; the
+ * product's time goes to stats.t_samples_ms.  EINVAL for null pointers,
+ * ldxi < n, m < 1, scale <= 0 or nugget < 0. */
+int mpchol_set_samples(mpchol_t h, const double *xi, int64_t ldxi, int64_t m, double scale, double nugget,
+                       int32_t on_device);
 
 /* Choose the precision of every tile and load Sigma into the work tiles.
  * Computes tile norms (FP64 on the device), applies `rule` with accuracy

@@ -111,6 +111,16 @@ __device__ inline double load_stored(const void *tile, int cls, int lo16, int t,
     }
 }
 
+// Inverse of tile_index: the lower tile (I, J) with I(I+1)/2 + J = t.
+__device__ inline void tile_ij(int64_t t, int &I, int &J)
+{
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
+    while ((int64_t)i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = (int)(t - (int64_t)i * (i + 1) / 2);
+}
+
 // XCD-aware block order: the hardware deals workgroups round-robin over the 8
 // XCDs; renumber so that consecutive logical blocks (which share operand rows)
 // run on the same XCD and its L2.

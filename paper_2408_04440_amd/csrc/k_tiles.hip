@@ -8,15 +8,6 @@
 
 namespace mpc {
 
-__device__ inline void tile_ij(int64_t t, int &I, int &J)
-{
-    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
-    while ((int64_t)i * (i + 1) / 2 > t) --i;
-    I = i;
-    J = (int)(t - (int64_t)i * (i + 1) / 2);
-}
-
 // Sigma at row r, column c of tile (I, J); identity in the padding beyond n.
 __device__ inline double source_value(const Tiles &T, const Source &S, int I, int J, int r, int c)
 {

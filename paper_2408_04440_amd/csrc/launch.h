@@ -63,6 +63,11 @@ void launch_residual_items(const Tiles &T, const Source &S, const int32_t *items
 void launch_estimate(const Tiles &T, const Source &S, bool sorted, uint64_t seed, double *scratch, float *zbuf,
                      double *out, hipStream_t st);
 int estimate_chunks(int64_t n);
+
+// ---- covariance from samples (k_samples.hip)
+// xp: (NT*b) x mp scratch (mp = m rounded up to 16); orig: the kept copy.
+int launch_cov_samples(const Tiles &T, const double *xi, int64_t ldxi, int64_t m, double scale, double nugget,
+                       double *xp, int64_t mp, double *orig, hipStream_t st);
 int estimate_probes();
 
 // ---- solve, sample (k_apply.hip)

@@ -328,6 +328,53 @@ int mpchol_set_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_devic
     return MPCHOL_OK;
 }
 
+int mpchol_set_samples(mpchol_t h, const double *xi, int64_t ldxi, int64_t m, double scale, double nugget,
+                       int32_t on_device)
+{
+    if (!h || !xi || ldxi < h->n || m < 1 || !(scale > 0) || !(nugget >= 0)) return MPCHOL_EINVAL;
+    HIPCHK(hipSetDevice(h->dev));
+    if (!h->orig) {
+        int rc = dalloc(&h->orig, h->ntile * h->slot_bytes);
+        if (rc) return rc;
+    }
+    const int64_t mp = (m + 15) / 16 * 16, ldp = (int64_t)h->nt * h->b;
+    double *xp = nullptr, *tmp = nullptr;
+    int rc = dalloc(&xp, (size_t)ldp * mp * 8);
+    if (rc) return rc;
+    const double *dx = xi;
+    if (!on_device) {
+        const size_t bytes = (size_t)ldxi * (size_t)m * 8;
+        rc = dalloc(&tmp, bytes);
+        if (rc) {
+            (void)hipFree(xp);
+            return rc;
+        }
+        if (hipMemcpyAsync(tmp, xi, bytes, hipMemcpyHostToDevice, h->st) != hipSuccess) {
+            (void)hipFree(xp);
+            (void)hipFree(tmp);
+            return MPCHOL_EHIP;
+        }
+        dx = tmp;
+    }
+    hipError_t e = hipEventRecord(h->ev[2], h->st);
+    launch_cov_samples(h->tiles(), dx, ldxi, m, scale, nugget, xp, mp, h->orig, h->st);
+    if (e == hipSuccess) e = hipEventRecord(h->ev[3], h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e == hipSuccess) e = hipGetLastError();
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
+    (void)hipFree(xp);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        hip_fail(e, "set_samples", __LINE__);
+        return MPCHOL_EHIP;
+    }
+    h->stats.t_samples_ms = ms;
+    h->src = 1;
+    h->state = S_SOURCE;
+    return MPCHOL_OK;
+}
+
 int mpchol_set_generator(mpchol_t h, const double *sigma, const double *x, double rho, double nugget)
 {
     if (!h || !sigma || !x || !(rho > 0) || !(nugget >= 0)) return MPCHOL_EINVAL;

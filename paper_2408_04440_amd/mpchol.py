@@ -42,7 +42,7 @@ class Stats(C.Structure):
                 ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_sample_ms", C.c_double),
                 ("t_residual_ms", C.c_double), ("t_gemm_ms", C.c_double * 4), ("gemm_launches", C.c_int64 * 4),
                 ("gemm_flops", C.c_double * 4), ("fallbacks", C.c_int32), ("rule_used", C.c_int32),
-                ("verify_first", C.c_double)]
+                ("verify_first", C.c_double), ("t_samples_ms", C.c_double)]
 
 
 _lib = None
@@ -74,6 +74,7 @@ def lib():
             "mpchol_destroy": (C.c_int, [vp]),
             "mpchol_set_matrix": (C.c_int, [vp, vp, i64, i32]),
             "mpchol_set_generator": (C.c_int, [vp, vp, vp, d, d]),
+            "mpchol_set_samples": (C.c_int, [vp, vp, i64, i64, d, d, i32]),
             "mpchol_precision_map": (C.c_int, [vp, i32, d, vp, vp]),
             "mpchol_factor": (C.c_int, [vp, C.POINTER(i64)]),
             "mpchol_logdet": (C.c_int, [vp, C.POINTER(d)]),
@@ -186,6 +187,19 @@ def mpchol_set_generator(h, sigma, x, rho, nugget):
     x = np.ascontiguousarray(x, dtype=np.float64)
     _chk(lib().mpchol_set_generator(h, sigma.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p), float(rho),
                                     float(nugget)), "mpchol_set_generator")
+
+
+def mpchol_set_samples(h, Xi, scale, nugget, m=None):
+    """Sigma = scale * Xi Xi^T + nugget I.  Xi: numpy n x m (host), or a
+    torch float64 column-major device view (Xi.T of a contiguous (m, n))."""
+    if isinstance(Xi, np.ndarray):
+        Xi = np.asfortranarray(Xi, dtype=np.float64)
+        rc = lib().mpchol_set_samples(h, Xi.ctypes.data_as(C.c_void_p), Xi.shape[0], Xi.shape[1], float(scale),
+                                      float(nugget), 0)
+    else:
+        rc = lib().mpchol_set_samples(h, _ptr(Xi), _colmajor_ld(Xi, Xi.shape[0]), int(Xi.shape[1] if m is None else m),
+                                      float(scale), float(nugget), 1)
+    _chk(rc, "mpchol_set_samples")
 
 
 def mpchol_precision_map(h, rule, eps=1e-9, user_map=None, nt=None):

@@ -68,6 +68,7 @@ def test_argument_validation_without_gpu():
     m = C.c_void_p()
     assert L.mpchol_mlp_create(None, 0, None) == -1
     assert L.mpchol_set_verify(None, 1, C.c_double(1e-9)) == -1
+    assert L.mpchol_set_samples(None, None, 0, 0, C.c_double(1.0), C.c_double(0.0), 0) == -1
 
 
 def test_product_never_imports_oracle():
