@@ -84,7 +84,9 @@ def lib():
         L.orc_tile_norms.argtypes = [i64, i64, dp, i64, dp, dp]
         L.orc_map_norm.argtypes = [i64, dp, d, d, i32, C.c_uint, i32, C.POINTER(C.c_uint8)]
         L.orc_mp_factor.restype = i64
-        L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32]
+        L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32, i32]
+        L.orc_split3.restype = C.c_float
+        L.orc_split3.argtypes = [d, i32]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
         L.orc_normal_draws.argtypes = [C.c_uint64, i64, dp, u32p]
         L.orc_mlp_nparam.restype = i64
@@ -254,11 +256,12 @@ def map_norm(fro2, total, eps, band=1, allowed=0xF, lo16=F16):
     return out
 
 
-def mp_factor(A, b, cmap, lo16=F16, order=0):
+def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0):
     """O2: (Lhat, info, tscale) -- the tile algorithm replayed with explicit rounding.
 
     cmap is an nt x nt class map (lower part used; 0 FP64, 1 FP32, 2 16-bit, 3 FP8);
-    order 0/1 sums the update products in increasing/decreasing order.
+    order 0/1 sums the update products in increasing/decreasing order;
+    lo32 = 1 forms FP32-class products from three-way BF16 splits.
     """
     A = _fortran(A)
     n = A.shape[0]
@@ -268,8 +271,13 @@ def mp_factor(A, b, cmap, lo16=F16, order=0):
     Lh = np.zeros((n, n), order="F")
     ts = np.zeros((nt, nt), dtype=np.int32, order="F")
     info = lib().orc_mp_factor(n, b, _dp(A), n, cmap.ctypes.data_as(C.POINTER(C.c_uint8)), lo16, _dp(Lh), n,
-                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order))
+                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order), int(lo32))
     return Lh, int(info), ts
+
+
+def split3(v):
+    """(hi, mid, lo): the three-way BF16 split of float(v)."""
+    return tuple(float(lib().orc_split3(float(v), p)) for p in range(3))
 
 
 # ---------------------------------------------------------------- Philox, draws

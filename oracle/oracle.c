@@ -468,6 +468,13 @@ void orc_map_norm(int64_t nt, const double *fro2, double total_fro, double eps, 
  *     SYRK(I,I) and FP64-class GEMM(I,J): W -= C64_I C64_J^T in FP64;
  *     FP32-class GEMM: acc = sum of float products (float adds, k order),
  *       W = round_f32(W - acc);
+ *       with lo32 = 1 the FP32 operands are split into three BF16 parts,
+ *       v = hi + mid + lo (hi = bf16(v), mid = bf16(v - hi), lo = bf16(v - hi
+ *       - mid), each step exact in FP32), and acc sums the six significant
+ *       part products -- pairs (mid,mid), (hi,lo), (lo,hi), (hi,mid),
+ *       (mid,hi), (hi,hi) in this order, each over k -- as exact float
+ *       products with float adds (the split-product scheme of Henry, Tang and
+ *       Heinecke, ARITH 2019, with the three smallest products dropped);
  *     16-bit/FP8-class GEMM: acc as above on the scaled copies,
  *       W = round_f32(W - acc * 2^-(t_I + t_J)).
  * order = 0 sums the update products in increasing c, order = 1 in
@@ -481,8 +488,20 @@ void orc_map_norm(int64_t nt, const double *fro2, double total_fro, double eps, 
  * ---------------------------------------------------------------------- */
 #define IDX(i, j) ((i) + (size_t)(j) * (size_t)np)
 
+/* Part (0 hi, 1 mid, 2 lo) of the three-way BF16 split of the float value v. */
+float orc_split3(double v, int part)
+{
+    const float f = (float)v;
+    const float hi = (float)orc_round(f, ORC_BF16);
+    if (part == 0) return hi;
+    const float r1 = f - hi;
+    const float mid = (float)orc_round(r1, ORC_BF16);
+    if (part == 1) return mid;
+    return (float)orc_round(r1 - mid, ORC_BF16);
+}
+
 int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const uint8_t *map, int lo16,
-                      double *Lhat, int64_t ldl, int32_t *tscale, int order)
+                      double *Lhat, int64_t ldl, int32_t *tscale, int order, int lo32)
 {
     int64_t nt = (n + b - 1) / b, np = nt * b;
     double *W = malloc(sizeof(double) * (size_t)np * np);
@@ -593,6 +612,20 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                             for (int64_t r = 0; r < b; ++r) acc64[r] += ci[r] * bj;
                         }
                         for (int64_t r = 0; r < b; ++r) W[IDX(i0 + r, j0 + s)] -= acc64[r];
+                    } else if (cls == ORC_P32 && lo32) {
+                        static const int pa[6] = {1, 0, 2, 0, 1, 0}, pb[6] = {1, 2, 0, 1, 0, 0};
+                        for (int64_t r = 0; r < b; ++r) acc32[r] = 0.0f;
+                        for (int t = 0; t < 6; ++t)
+                            for (int64_t cc = 0; cc < b; ++cc) {
+                                int64_t c = order ? b - 1 - cc : cc;
+                                float bj = orc_split3(CJ[(j0 + s) + (size_t)c * np], pb[t]);
+                                const double *ci = CI + i0 + (size_t)c * np;
+                                for (int64_t r = 0; r < b; ++r) acc32[r] += orc_split3(ci[r], pa[t]) * bj;
+                            }
+                        for (int64_t r = 0; r < b; ++r) {
+                            float w = (float)W[IDX(i0 + r, j0 + s)];
+                            W[IDX(i0 + r, j0 + s)] = (double)(w - acc32[r]);
+                        }
                     } else {
                         for (int64_t r = 0; r < b; ++r) acc32[r] = 0.0f;
                         for (int64_t cc = 0; cc < b; ++cc) {

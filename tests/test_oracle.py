@@ -469,3 +469,50 @@ def test_cov_samples_symmetric_psd(orc):
     S = orc.cov_samples(xi, 1.0 / 25, 1e-6)
     assert np.array_equal(S, S.T)
     assert np.linalg.eigvalsh(S).min() >= 1e-6 * (1 - 1e-6)
+
+
+# ---------------------------------------------------------------- three-way BF16 split products
+def test_split3_reconstructs_every_float(orc):
+    """hi + mid + lo == float(v) exactly, each part a BF16 value and each
+    smaller than the previous by at least 2^8 (the split that makes the six
+    part products carry a float product's information)."""
+    z = synth.normal(71, 3000)
+    e = synth.uniform01(72, 3000) * 60.0 - 30.0
+    for v in z * np.exp(e):
+        v32 = float(np.float32(v))
+        hi, mid, lo = orc.split3(v)
+        assert hi + mid + lo == v32
+        for p in (hi, mid, lo):
+            assert orc.round_to(p, orc.BF16) == p
+        assert abs(mid) <= abs(hi) * 2.0 ** -8 and abs(lo) <= abs(mid) * 2.0 ** -8
+
+
+def test_mp_factor_split_integer_exact(orc):
+    """A = L0 L0^T with small integers and every off-band tile FP32 under the
+    split products: the replay returns L0 exactly."""
+    n, b = 384, 128
+    L0 = synth.int_lower(n, 13)
+    A = L0 @ L0.T
+    nt = n // b
+    cmap = np.tril(np.ones((nt, nt), np.uint8), -1)
+    Lh, info, _ = orc.mp_factor(A, b, cmap, lo32=1)
+    assert info == 0 and np.array_equal(Lh, L0)
+
+
+def test_mp_factor_split_close_to_fp32(orc):
+    """On a covariance with a map using every class, the split-product replay
+    stays within a few times the spread between two summation orders of the
+    plain FP32 replay (the three dropped part products are of the order of a
+    float rounding)."""
+    sigma, x = synth.workload(24)
+    A = orc.cov_dense(sigma, x, 5.0, 1e-2)
+    b, nt = 64, 9
+    u = synth.uniform01(73, nt * nt).reshape(nt, nt)
+    cmap = np.tril(np.floor(u * 4).astype(np.uint8), -1)
+    L0, _, _ = orc.mp_factor(A, b, cmap, order=0)
+    L1, _, _ = orc.mp_factor(A, b, cmap, order=1)
+    Ls, info, _ = orc.mp_factor(A, b, cmap, lo32=1)
+    assert info == 0
+    d_oo = np.linalg.norm(L0 - L1) / np.linalg.norm(L0)
+    d_so = np.linalg.norm(Ls - L0) / np.linalg.norm(L0)
+    assert 0 < d_so <= 4.0 * d_oo
