@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
     ap.add_argument("--eps", type=float, default=None, help="override the workload's accuracy threshold")
+    ap.add_argument("--lo32", default="fp32", choices=["fp32", "bf16x3"],
+                    help="FP32-class update arithmetic: FP32 MFMA or three-way BF16 split products")
     ap.add_argument("--band-variant", type=int, default=None, choices=[1, 2, 3],
                     help="band rule variant: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP")
     ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
@@ -183,6 +185,7 @@ def main():
     stream = torch.cuda.current_stream()
     need_w = (args.rule or "").startswith("learned") or "learned" in args.compare
     extra = {} if args.band_variant is None else {"band_variant": args.band_variant}
+    extra["lo32"] = M.LO32_BF16X3 if args.lo32 == "bf16x3" else M.LO32_FP32
     h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
                         verify=2 if need_w else 0, verify_eps=eps, **extra)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
@@ -323,7 +326,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"SH covariance L={L} (N={n}), tile {tile}, rho={rho}, nugget 1e-8, "
                                f"{[k for k, v in RULES.items() if v == rule][0]} rule eps={eps}, classes {cfg['label']}",
-                   "N": n, "tile": tile, "nt": nt, "rho": rho, "eps": eps,
+                   "N": n, "tile": tile, "nt": nt, "rho": rho, "eps": eps, "fp32_class": args.lo32,
                    "step": "generate+norms+map+factor+logdet" + ("+1000 draws" if cfg["draws"] else "")
                            + (f"+solve({cfg['rhs']} rhs)" if cfg["rhs"] else "")},
         "t_factor_ms": round(t_med, 2),

@@ -54,6 +54,8 @@ extern "C" {
 /* which 16-bit format the P16 class uses */
 #define MPCHOL_LO16_F16 0
 #define MPCHOL_LO16_BF16 1
+#define MPCHOL_LO32_FP32 0
+#define MPCHOL_LO32_BF16X3 1
 
 /* precision-map rules */
 #define MPCHOL_RULE_FP64 0    /* every tile FP64 (the plain FP64 path) */
@@ -80,6 +82,10 @@ typedef struct mpchol_opts {
                             0 off, 1 exact FP64 residual, 2 randomized estimate (64 probes, 3-sigma margin) */
     double verify_eps;   /* backward-error budget used by verify */
     int32_t profile;     /* nonzero: time every update-GEMM launch with events (adds event overhead) */
+    int32_t lo32;        /* arithmetic of the FP32-class updates: MPCHOL_LO32_FP32 (FP32 MFMA) or
+                            MPCHOL_LO32_BF16X3 (each FP32 operand split into three BF16 parts, the six
+                            significant part products on the BF16 MFMA, FP32 accumulation); storage,
+                            conversion and the map rule are the same for both */
 } mpchol_opts;
 
 typedef struct mpchol_stats {

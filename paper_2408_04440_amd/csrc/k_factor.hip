@@ -350,6 +350,73 @@ __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const
         }
 }
 
+// FP32-class update from three-way BF16 splits of the operands (v = hi + mid
+// + lo, the FP32 copy exactly): the six significant part products (mid,mid),
+// (hi,lo), (lo,hi), (hi,mid), (mid,hi), (hi,hi), smallest first, each over
+// the full K on the BF16 MFMA with FP32 accumulation; the three products
+// below a float rounding of the result -- (mid,lo), (lo,mid), (lo,lo) -- are
+// dropped.  For a pair of steps the two panels' products of one kind follow
+// each other.  Operands: panel + I*3*b*b + part*b*b, row-major b x b.
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void update_split_kernel(Tiles Tt, const uint16_t *panel0,
+                                                                    const uint16_t *panel1, const int32_t *items)
+{
+    typedef RMShape<RM_BF16, BM, BN, BK, WM, WN> S;
+    extern __shared__ __align__(16) char smem_raw[];
+    const int b = Tt.b;
+    const int tmn = b / BM, tnn = b / BN;
+    const int64_t lg = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = (int)(lg / (tmn * tnn));
+    const int rem = (int)(lg % (tmn * tnn));
+    const int tm = rem % tmn, tn = rem / tmn;
+    const int32_t it = items[item];
+    const int I = it >> 16, J = it & 0xFFFF;
+    const int64_t bb = (int64_t)b * b, bb3 = 3 * bb;
+    float4_t acc[S::MB][S::NB];
+#pragma unroll
+    for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < S::NB; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    const int npan = panel1 ? 2 : 1;
+#pragma nounroll
+    for (int s = 0; s < 6 * npan; ++s) {
+        const int t = s / npan;                      // kind of product, smallest first
+        const int pa = (0x010201 >> (4 * t)) & 0xF;  // part of the I operand: 1 0 2 0 1 0
+        const int pb = (0x001021 >> (4 * t)) & 0xF;  // part of the J operand: 1 2 0 1 0 0
+        const uint16_t *pn = (s % npan) ? panel1 : panel0;
+        rm_block<RM_BF16, BM, BN, BK, WM, WN>(pn + I * bb3 + pa * bb + (int64_t)tm * BM * b, b,
+                                              pn + J * bb3 + pb * bb + (int64_t)tn * BN * b, b, b, acc,
+                                              (uint8_t *)smem_raw);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
+    float *C = (float *)(Tt.slots + tile_index(I, J) * Tt.slot_bytes) + tm * BM + (int64_t)tn * BN * b;
+#pragma unroll
+    for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < S::NB; ++n) {
+            int r = wm * (BM / WM) + m * 16 + 4 * gg, c = wn * (BN / WN) + n * 16 + gi;
+            float *p = C + r + (int64_t)c * b;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) p[v] -= acc[m][n][v];
+        }
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+static void launch_split(const Tiles &T_, const uint16_t *panel0, const uint16_t *panel1, const int32_t *items,
+                         int nitems, hipStream_t st)
+{
+    typedef RMShape<RM_BF16, BM, BN, BK, WM, WN> S;
+    auto k = update_split_kernel<BM, BN, BK, WM, WN>;
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::SMEM);
+        attr = true;
+    }
+    const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel0, panel1, items);
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN>
 static void launch_cm(const Tiles &T_, const T *panel0, const T *panel1, const int32_t *items, int nitems,
                       hipStream_t st)
@@ -397,8 +464,14 @@ void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const
     switch (q) {
     case P64: launch_cm<double, 128, 128, 16, 4, 4>(T, P.p64, P2 ? P2->p64 : nullptr, items, nitems, st); break;
     case P32:
-        if ((T.b % 256) == 0) launch_cm<float, 256, 128, 16, 4, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
-        else launch_cm<float, 128, 128, 16, 2, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
+        if (T.lo32) {
+            if (big) launch_split<256, 256, 64, 4, 4>(T, P.p32s, P2 ? P2->p32s : nullptr, items, nitems, st);
+            else launch_split<128, 128, 64, 2, 2>(T, P.p32s, P2 ? P2->p32s : nullptr, items, nitems, st);
+        } else if ((T.b % 256) == 0) {
+            launch_cm<float, 256, 128, 16, 4, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
+        } else {
+            launch_cm<float, 128, 128, 16, 2, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
+        }
         break;
     case P16: {
         const uint16_t *p2 = P2 ? P2->p16 : nullptr;

@@ -111,8 +111,9 @@ __global__ __launch_bounds__(256) void panel_max_kernel(Tiles T, Panel P, int k)
 // The TRSM output X (FP64, in p64[I]) becomes the stored value S of tile
 // (I,k) in its class -- FP64: X; FP32: (float)X; 16-bit/FP8: the scaled,
 // rounded code of (float)X with t from max|(float)X| -- and every class q
-// in qmask[I] gets its copy: FP64 S, FP32 (float)S, 16-bit/FP8 the code of
-// S with the copy's own scale (row-major for these two).
+// in qmask[I] gets its copy: FP64 S, FP32 (float)S (or, with the split
+// products, its three BF16 parts), 16-bit/FP8 the code of S with the copy's
+// own scale (row-major for the 16-bit, 8-bit and split copies).
 __global__ __launch_bounds__(256) void convert_kernel(Tiles T, Panel P, int k, const uint8_t *qmask)
 {
     __shared__ double xs[64][65];  // xs[c][r]
@@ -164,9 +165,10 @@ __global__ __launch_bounds__(256) void convert_kernel(Tiles T, Panel P, int k, c
         }
         xs[c][r] = Sv;
         if (mask & 1) x64[off] = Sv;
-        if (mask & 2) P.p32[(int64_t)I * bb + off] = (float)Sv;
+        if ((mask & 2) && !T.lo32) P.p32[(int64_t)I * bb + off] = (float)Sv;
     }
-    if (mask & 12) {
+    const bool split = (mask & 2) && T.lo32;
+    if ((mask & 12) || split) {
         __syncthreads();
         for (int e = threadIdx.x; e < 4096; e += 256) {
             int c = e & 63, r = e >> 6;
@@ -174,6 +176,17 @@ __global__ __launch_bounds__(256) void convert_kernel(Tiles T, Panel P, int k, c
             int64_t roff = (int64_t)(sr * 64 + r) * b + (sc * 64 + c);
             if (mask & 4) P.p16[(int64_t)I * bb + roff] = (uint16_t)encode_class(Sv, P16, lo16, tq[P16]);
             if (mask & 8) P.p8[(int64_t)I * bb + roff] = (uint8_t)encode_class(Sv, P8, lo16, tq[P8]);
+            if (split) {  // FP32 copy as hi + mid + lo, each step exact in FP32
+                const float f = (float)Sv;
+                const uint16_t hi = f32_to_bf16(f);
+                const float r1 = f - bf16_to_f32(hi);
+                const uint16_t mid = f32_to_bf16(r1);
+                const uint16_t lo = f32_to_bf16(r1 - bf16_to_f32(mid));
+                uint16_t *d = P.p32s + (int64_t)I * 3 * bb + roff;
+                d[0] = hi;
+                d[bb] = mid;
+                d[2 * bb] = lo;
+            }
         }
     }
 }

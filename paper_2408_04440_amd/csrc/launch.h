@@ -14,6 +14,7 @@ struct Tiles {
     const uint8_t *map;   // nt*nt classes, entry I + J*nt
     int32_t *tscale;      // nt*nt stored scale exponents
     int lo16;
+    int lo32;             // FP32-class updates: 0 FP32 MFMA, 1 three-way BF16 split products
 };
 
 // Source of Sigma: the generator (sigma, x, rho, nugget) or a kept FP64 copy
@@ -32,6 +33,7 @@ struct Panel {
     uint8_t *p8;      // row-major (k contiguous)
     unsigned long long *pmax;  // nt: max |X| of the TRSM output of tile I (FP64 bits)
     int32_t *pscale;           // nt*4: scale exponent of the class-q copy of tile I
+    uint16_t *p32s;            // lo32 split: hi, mid, lo BF16 parts of the FP32 copy, each b*b row-major
 };
 
 // ---- tiles (k_tiles.hip)

@@ -52,6 +52,7 @@ struct mpchol_handle {
     // panel copies, four sets (column mod 4: the pair being applied and the pair being factored)
     double *p64 = nullptr;
     float *p32 = nullptr;
+    uint16_t *p32s = nullptr;  // three BF16 parts of the FP32 copies (lo32 = BF16x3)
     uint16_t *p16 = nullptr;
     uint8_t *p8 = nullptr;
     unsigned long long *pmax = nullptr;
@@ -99,6 +100,7 @@ struct mpchol_handle {
         T.map = d_map;
         T.tscale = d_tscale;
         T.lo16 = o.lo16;
+        T.lo32 = o.lo32;
         return T;
     }
     Source source() const
@@ -117,6 +119,7 @@ struct mpchol_handle {
         Panel P;
         P.p64 = p64 + set * nt * bb;
         P.p32 = p32 + set * nt * bb;
+        P.p32s = p32s ? p32s + set * nt * 3 * bb : nullptr;
         P.p16 = p16 + set * nt * bb;
         P.p8 = p8 + set * nt * bb;
         P.pmax = pmax + set * nt;
@@ -158,7 +161,7 @@ static int dalloc(T **p, size_t bytes)
 
 static void release(mpchol_handle *h)
 {
-    void *ptrs[] = {h->slots, h->orig, h->d_sigma, h->d_x, h->p64, h->p32, h->p16, h->p8, h->pmax, h->pscale,
+    void *ptrs[] = {h->slots, h->orig, h->d_sigma, h->d_x, h->p64, h->p32, h->p32s, h->p16, h->p8, h->pmax, h->pscale,
                     h->d_map, h->d_tscale, h->d_fro2, h->d_amax, h->d_info, h->d_scalar, h->d_items, h->d_qmask,
                     h->d_all_items, h->d_partial, h->d_tres2, h->d_params, h->d_feats, h->d_est, h->d_zbuf};
     for (void *p : ptrs)
@@ -186,6 +189,7 @@ void mpchol_default_opts(mpchol_opts *o)
     o->verify = 0;
     o->verify_eps = 1e-9;
     o->profile = 0;
+    o->lo32 = MPCHOL_LO32_FP32;
 }
 
 const char *mpchol_last_error(void) { return g_last_error; }
@@ -216,6 +220,7 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     if (o) opt = *o;
     else mpchol_default_opts(&opt);
     if (opt.lo16 != MPCHOL_LO16_F16 && opt.lo16 != MPCHOL_LO16_BF16) return MPCHOL_EINVAL;
+    if (opt.lo32 != MPCHOL_LO32_FP32 && opt.lo32 != MPCHOL_LO32_BF16X3) return MPCHOL_EINVAL;
     if (opt.band < 0) return MPCHOL_EINVAL;
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
@@ -243,6 +248,7 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     A(dalloc(&h->slots, h->ntile * h->slot_bytes));
     A(dalloc(&h->p64, 4 * nt * bb * 8));
     A(dalloc(&h->p32, 4 * nt * bb * 4));
+    if (h->o.lo32 == MPCHOL_LO32_BF16X3) A(dalloc(&h->p32s, 4 * nt * bb * 3 * 2));
     A(dalloc(&h->p16, 4 * nt * bb * 2));
     A(dalloc(&h->p8, 4 * nt * bb));
     A(dalloc(&h->pmax, 4 * nt * 8));

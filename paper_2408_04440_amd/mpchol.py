@@ -20,6 +20,7 @@ P64, P32, P16, P8 = 0, 1, 2, 3
 LO16_F16, LO16_BF16 = 0, 1
 RULE_FP64, RULE_NORM, RULE_BAND, RULE_USER, RULE_LEARNED = 0, 1, 2, 3, 4
 BAND_DP_SP, BAND_DP_SP_HP, BAND_DP_HP = 1, 2, 3
+LO32_FP32, LO32_BF16X3 = 0, 1
 MLP_NPARAM = 4996
 
 
@@ -33,7 +34,7 @@ class MpcholError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("lo16", C.c_int32), ("band", C.c_int32),
                 ("allowed", C.c_uint32), ("band_variant", C.c_int32), ("verify", C.c_int32),
-                ("verify_eps", C.c_double), ("profile", C.c_int32)]
+                ("verify_eps", C.c_double), ("profile", C.c_int32), ("lo32", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -159,10 +160,12 @@ def mpchol_default_opts() -> Opts:
 
 
 def mpchol_create(n, tile, device=0, stream=None, lo16=LO16_F16, band=1, allowed=0xF, band_variant=BAND_DP_HP,
-                  verify=0, verify_eps=1e-9, profile=0):
+                  verify=0, verify_eps=1e-9, profile=0, lo32=None):
     o = mpchol_default_opts()
     o.device, o.stream, o.lo16, o.band = device, _stream_ptr(stream), lo16, band
     o.allowed, o.band_variant, o.verify, o.verify_eps, o.profile = allowed, band_variant, verify, verify_eps, profile
+    if lo32 is not None:
+        o.lo32 = lo32
     h = C.c_void_p()
     _chk(lib().mpchol_create(C.byref(h), int(n), int(tile), C.byref(o)), "mpchol_create")
     return h
