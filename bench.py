@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
     ap.add_argument("--eps", type=float, default=None, help="override the workload's accuracy threshold")
-    ap.add_argument("--lo32", default="fp32", choices=["fp32", "bf16x3"],
+    ap.add_argument("--lo32", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="FP32-class update arithmetic: FP32 MFMA or three-way BF16 split products")
     ap.add_argument("--band-variant", type=int, default=None, choices=[1, 2, 3],
                     help="band rule variant: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP")

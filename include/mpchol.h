@@ -85,7 +85,7 @@ typedef struct mpchol_opts {
     int32_t lo32;        /* arithmetic of the FP32-class updates: MPCHOL_LO32_FP32 (FP32 MFMA) or
                             MPCHOL_LO32_BF16X3 (each FP32 operand split into three BF16 parts, the six
                             significant part products on the BF16 MFMA, FP32 accumulation); storage,
-                            conversion and the map rule are the same for both */
+                            conversion and the map rule are the same for both; default BF16X3 */
 } mpchol_opts;
 
 typedef struct mpchol_stats {

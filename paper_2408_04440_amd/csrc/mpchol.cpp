@@ -189,7 +189,7 @@ void mpchol_default_opts(mpchol_opts *o)
     o->verify = 0;
     o->verify_eps = 1e-9;
     o->profile = 0;
-    o->lo32 = MPCHOL_LO32_FP32;
+    o->lo32 = MPCHOL_LO32_BF16X3;
 }
 
 const char *mpchol_last_error(void) { return g_last_error; }

@@ -17,6 +17,12 @@ parameters are not available):
   factor), drawn with seed 0;
 * right-hand sides B ~ N(0, 1) with seed 1; caller-side draws z ~ N(0, 1) with seed 2.
 
+SHT inputs (Sec. III.A.2 and III.B; the ERA5 fields are not available): real
+coefficient vectors f_t of length L^2 in the same index order, N(0,1) scaled
+by (1+l)^-1 (seed 5), and white-noise grid fields N(0,1) of N_theta x N_phi
+points (seed 6) standing in for the stochastic component, which is not
+band-limited.
+
 Random numbers: splitmix64 (Steele, Lea & Flood, "Fast splittable
 pseudorandom number generators", OOPSLA 2014) -> 53-bit uniforms ->
 Box-Muller (Box & Muller 1958) in FP64.
@@ -34,6 +40,8 @@ SEED_RHS = 1
 SEED_DRAWS = 2
 SEED_MLP_INIT = 3
 SEED_SAMPLES = 4
+SEED_SHT_COEFFS = 5
+SEED_SHT_FIELD = 6
 
 
 def splitmix64(seed: int, count: int) -> np.ndarray:
@@ -142,3 +150,14 @@ def features_toy(count: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     8 features ~ U(-1, 1); class = index of the largest of the first 4."""
     u = uniform01(seed, count * 8).reshape(count, 8) * 2.0 - 1.0
     return u.astype(np.float32), np.argmax(u[:, :4], axis=1).astype(np.int32)
+
+
+def sht_coeffs(L: int, T: int, seed: int = SEED_SHT_COEFFS) -> np.ndarray:
+    """T real coefficient vectors (row t = f_t, length L^2), N(0,1) / (1 + l)."""
+    l = sh_degrees(L).astype(np.float64)
+    return normal(seed, T * L * L).reshape(T, L * L) / (1.0 + l)[None, :]
+
+
+def sht_fields(T: int, ntheta: int, nphi: int, seed: int = SEED_SHT_FIELD) -> np.ndarray:
+    """T white-noise fields N(0,1) on an N_theta x N_phi grid (longitude fastest)."""
+    return normal(seed, T * ntheta * nphi).reshape(T, ntheta, nphi)

@@ -87,3 +87,4 @@ def test_default_opts():
 
     o = M.mpchol_default_opts()
     assert o.band == 1 and o.allowed == 0xF and o.lo16 == M.LO16_F16 and o.verify_eps == 1e-9
+    assert o.lo32 == M.LO32_BF16X3

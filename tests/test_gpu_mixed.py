@@ -36,7 +36,7 @@ def test_norm_rule_map_scales_and_factor(orc, L, tile, rho, eps, lo16):
     fro2, amax, tot = orc.tile_norms(A, tile)
     mo = orc.map_norm(fro2, tot, eps, band=1, allowed=0xF, lo16=olo)
     mod = M()
-    h = mod.mpchol_create(n, tile, lo16=lo16)
+    h = mod.mpchol_create(n, tile, lo16=lo16, lo32=mod.LO32_FP32)
     try:
         mod.mpchol_set_generator(h, sigma, x, rho, 1e-8)
         mg = mod.mpchol_precision_map(h, mod.RULE_NORM, eps)
@@ -76,7 +76,9 @@ def test_norm_rule_map_scales_and_factor(orc, L, tile, rho, eps, lo16):
 
 @pytest.mark.parametrize("n,tile,seed,lo16", [(1024, 128, 31, 0), (1000, 128, 32, 1), (1280, 256, 33, 0)])
 def test_user_map_all_classes_against_replay(orc, n, tile, seed, lo16):
-    """A random map using every class, on a well-conditioned covariance."""
+    """A random map using every class, on a well-conditioned covariance (FP32
+    MFMA for the FP32-class updates; the split products have their own replay
+    test)."""
     olo = orc.F16 if lo16 == 0 else orc.BF16
     L = int(np.ceil(np.sqrt(n)))
     sigma, x = synth.workload(L)
@@ -86,7 +88,7 @@ def test_user_map_all_classes_against_replay(orc, n, tile, seed, lo16):
     u = synth.uniform01(seed, nt * nt).reshape(nt, nt)
     um = np.asfortranarray(np.tril(np.floor(u * 4).astype(np.uint8), -1))
     mod = M()
-    h = mod.mpchol_create(n, tile, lo16=lo16)
+    h = mod.mpchol_create(n, tile, lo16=lo16, lo32=mod.LO32_FP32)
     try:
         mod.mpchol_set_matrix(h, A)
         mod.mpchol_precision_map(h, mod.RULE_USER, 1e-9, um)
