@@ -279,6 +279,63 @@ int mpchol_mlp_train_step(mpchol_mlp_t m, const float *X, const int32_t *y, int6
 /* logits (device nb x 4 row-major) and/or argmax classes (device nb int32) */
 int mpchol_mlp_predict(mpchol_mlp_t m, const float *X, int64_t nb, float *logits, int32_t *cls);
 
+/* ------------------------------------------------------------------ SHT
+ * Spherical harmonic transform of real fields and its inverse, batched over
+ * time steps, in FP64: the forward transform of Sec. III.A.1 ("Modeling in
+ * the Spherical Harmonic Domain": G_m by FFT along longitude, K_{m,m'} by FFT
+ * along the colatitude extended to (pi, 2 pi) with G_m(2 pi - theta) =
+ * (-1)^m G_m(theta), then the sums with S_{l,m,m''} and I(q), the Wigner-d
+ * functions at pi/2 precomputed as in Sec. III.A.2), and the inverse used to
+ * turn emulated coefficient vectors into fields (Sec. III.B).
+ *   Grid: N_theta colatitudes theta_j = j pi / (N_theta - 1) (both poles) and
+ *   N_phi longitudes phi_k = 2 pi k / N_phi.  A field is N_theta x N_phi
+ *   doubles, longitude fastest; T fields are contiguous (T x N_theta x N_phi).
+ *   Coefficients: z_{l,m} = integral of Z conj(Y_lm) over the sphere, Y_lm
+ *   orthonormal with the Condon-Shortley phase, 0 <= l < L.  Each time step
+ *   has the real vector f_t of length L^2 (T vectors contiguous, T x L^2):
+ *   index l^2 + l holds z_{l,0}; for 0 < m <= l, index l^2 + l + m holds
+ *   sqrt(2) Re z_{l,m} and index l^2 + l - m holds sqrt(2) Im z_{l,m} (a real
+ *   field has z_{l,-m} = (-1)^m conj z_{l,m}; |f_t| = the L2 norm of the
+ *   band-limited part of the field).
+ *   The inverse evaluates Z = sum_{l<L} sum_m z_{l,m} Y_lm on the grid (the
+ *   longitude synthesis carries the 1/(2 pi) of the inverse Fourier series).
+ *   Poles: the extension's symmetry forces G_m = 0 at theta = 0 and pi for
+ *   odd m, and those samples are taken as zero (a field single-valued at the
+ *   poles, constant along the first and last rows, has them).
+ *   For fields band-limited at L the forward transform returns their
+ *   coefficients and the inverse reproduces them, up to FP64 rounding
+ *   (N_theta > L and N_phi >= 2L - 1 make the paper's FFT steps exact); other
+ *   fields go through the same linear map (their higher degrees alias). */
+typedef struct mpchol_sht *mpchol_sht_t;
+
+/* Create a transform object on `device`, ordered on `stream` (NULL: the
+ * default stream): computes d^l_{k,m}(pi/2) (recursion in the first index),
+ * the forward and inverse tables (about L^3 / 2 doubles each) and work
+ * buffers for up to tmax time steps per call.  Requires 1 <= L <= 1024,
+ * N_theta > L, N_phi >= 2L - 1, N_phi and 2 N_theta - 2 products of 2, 3 and 5
+ * of at most 4096, 1 <= tmax <= 2^20.  Errors: MPCHOL_EINVAL (sizes, with a
+ * message from mpchol_sht_last_error), MPCHOL_ENOMEM, MPCHOL_EHIP.
+ * Synchronizes the stream once. */
+int mpchol_sht_create(mpchol_sht_t *s, int32_t L, int32_t ntheta, int32_t nphi, int32_t tmax, int32_t device,
+                      void *stream);
+int mpchol_sht_destroy(mpchol_sht_t s);
+
+/* Forward transform: device Z (T x N_theta x N_phi) -> device f (T x L^2),
+ * 0 <= T <= tmax (T = 0 does nothing).  Only enqueues.  The object's work
+ * buffers are shared by its calls: calls on one object must not overlap. */
+int mpchol_sht_forward(mpchol_sht_t s, const double *Z, int64_t T, double *f);
+
+/* Inverse transform: device f (T x L^2) -> device Z (T x N_theta x N_phi).
+ * Same rules as the forward call. */
+int mpchol_sht_inverse(mpchol_sht_t s, const double *f, int64_t T, double *Z);
+
+/* Device bytes of the tables and of the work buffers, and the FP64 GEMM flops
+ * per time step of one transform (unpadded; each argument may be NULL). */
+int mpchol_sht_info(mpchol_sht_t s, int64_t *table_bytes, int64_t *work_bytes, int64_t *gemm_flops_per_step);
+
+/* Message of the last failed mpchol_sht_create on this thread. */
+const char *mpchol_sht_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

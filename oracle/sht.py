@@ -1,6 +1,6 @@
 """CPU oracle of the spherical harmonic transform -- TEST INFRASTRUCTURE ONLY.
 
-Plain FP64 numpy implementation of the forward SHT (Sec. III.A.2, "Modeling
+Plain FP64 numpy implementation of the forward SHT (Sec. III.A.1, "Modeling
 in the Spherical Harmonic Domain": FFT along longitude, extension of G_m to
 colatitudes in (pi, 2 pi), inverse FFT along the extended colatitude for
 K_{m,m'}, then the two sums of the coefficient equation with S_{l,m,m''} and
@@ -19,6 +19,11 @@ Conventions (readings, stated once):
   <l m'| exp(-i beta J_y) |l m>.
 * inverse over longitude: Z(theta, phi) = (1 / 2 pi) sum_m G_m(theta) e^{i m phi}
   (the inverse of G_m = int Z e^{-i m phi} dphi).
+* poles: the extension G_m(2 pi - theta) = (-1)^m G_m(theta), continued to
+  theta = 0 and pi, forces G_m = 0 there for odd m; the pole samples of odd
+  orders are taken as zero before the colatitude FFT.  A field that is
+  single-valued at the poles (constant along the first and last grid rows),
+  in particular any band-limited field, is unaffected.
 * real coefficient vector f of length L^2 (the paper's f_t): index l^2 + l holds
   z_{l,0}; for m > 0, index l^2 + l + m holds sqrt(2) Re z_{l,m} and index
   l^2 + l - m holds sqrt(2) Im z_{l,m}.  For a real field z_{l,-m} =
@@ -132,6 +137,11 @@ def K_from_G(G: np.ndarray, L: int, orders=None) -> np.ndarray:
     ext = np.zeros((M, G.shape[1]), dtype=complex)
     ext[:ntheta] = G
     par = np.where(orders % 2 == 0, 1.0, -1.0)
+    # the extension's symmetry forces G_m = 0 at both poles for odd m (a
+    # field on the sphere, single-valued at a pole, has it); pole samples of
+    # odd orders are taken as zero
+    ext[0, par < 0] = 0.0
+    ext[ntheta - 1, par < 0] = 0.0
     for j in range(ntheta, M):
         ext[j] = par * G[M - j]
     F = np.fft.fft(ext, axis=0) / M  # coefficient of e^{+i m' theta_j}

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libmpchol.so")
 
 OK, NOT_SPD = 0, 1
+EINVAL, ENOMEM, EHIP, EORDER, EBUDGET, EUNSUPPORTED = -1, -2, -3, -4, -5, -6
 P64, P32, P16, P8 = 0, 1, 2, 3
 LO16_F16, LO16_BF16 = 0, 1
 RULE_FP64, RULE_NORM, RULE_BAND, RULE_USER, RULE_LEARNED = 0, 1, 2, 3, 4
@@ -101,6 +102,12 @@ def lib():
             "mpchol_mlp_grad": (C.c_int, [vp, vp, vp, i64, vp, C.c_float, vp, C.POINTER(C.c_float)]),
             "mpchol_mlp_train_step": (C.c_int, [vp, vp, vp, i64, vp, C.c_float, C.c_float, C.POINTER(C.c_float)]),
             "mpchol_mlp_predict": (C.c_int, [vp, vp, i64, vp, vp]),
+            "mpchol_sht_create": (C.c_int, [C.POINTER(vp), i32, i32, i32, i32, i32, vp]),
+            "mpchol_sht_destroy": (C.c_int, [vp]),
+            "mpchol_sht_forward": (C.c_int, [vp, vp, i64, vp]),
+            "mpchol_sht_inverse": (C.c_int, [vp, vp, i64, vp]),
+            "mpchol_sht_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]),
+            "mpchol_sht_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -354,3 +361,49 @@ def mpchol_mlp_train_step(m, X, y, cw, alpha, lr, want_loss=True):
 
 def mpchol_mlp_predict(m, X, logits=None, cls=None):
     _chk(lib().mpchol_mlp_predict(m, _ptr(X), X.shape[0], _ptr(logits), _ptr(cls)), "mpchol_mlp_predict")
+
+
+# ------------------------------------------------------------------------ SHT
+def mpchol_sht_create(L, ntheta, nphi, tmax, device=0, stream=None):
+    """Transform object for band limit L on an N_theta x N_phi grid, up to tmax
+    fields per call."""
+    s = C.c_void_p()
+    rc = lib().mpchol_sht_create(C.byref(s), int(L), int(ntheta), int(nphi), int(tmax), int(device),
+                                 _stream_ptr(stream))
+    if rc < 0:
+        raise MpcholError(rc, "mpchol_sht_create: " + lib().mpchol_sht_last_error().decode())
+    return s
+
+
+def mpchol_sht_destroy(s):
+    if s:
+        lib().mpchol_sht_destroy(s)
+
+
+def _sht_check(t, shape, what):
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous tensor of shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def mpchol_sht_forward(s, Z, f, L):
+    """device Z (T, N_theta, N_phi) float64 -> device f (T, L^2) float64."""
+    T = Z.shape[0]
+    _sht_check(f, (T, L * L), "f")
+    if not Z.is_contiguous():
+        raise ValueError("Z must be contiguous")
+    _chk(lib().mpchol_sht_forward(s, _ptr(Z), int(T), _ptr(f)), "mpchol_sht_forward")
+
+
+def mpchol_sht_inverse(s, f, Z, L):
+    """device f (T, L^2) float64 -> device Z (T, N_theta, N_phi) float64."""
+    T = f.shape[0]
+    _sht_check(f, (T, L * L), "f")
+    if not Z.is_contiguous() or Z.shape[0] != T:
+        raise ValueError("Z must be contiguous with T fields")
+    _chk(lib().mpchol_sht_inverse(s, _ptr(f), int(T), _ptr(Z)), "mpchol_sht_inverse")
+
+
+def mpchol_sht_info(s):
+    tb, wb, fl = C.c_int64(), C.c_int64(), C.c_int64()
+    _chk(lib().mpchol_sht_info(s, C.byref(tb), C.byref(wb), C.byref(fl)), "mpchol_sht_info")
+    return {"table_bytes": tb.value, "work_bytes": wb.value, "gemm_flops_per_step": fl.value}

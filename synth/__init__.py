@@ -17,7 +17,7 @@ parameters are not available):
   factor), drawn with seed 0;
 * right-hand sides B ~ N(0, 1) with seed 1; caller-side draws z ~ N(0, 1) with seed 2.
 
-SHT inputs (Sec. III.A.2 and III.B; the ERA5 fields are not available): real
+SHT inputs (Sec. III.A.1 and III.B; the ERA5 fields are not available): real
 coefficient vectors f_t of length L^2 in the same index order, N(0,1) scaled
 by (1+l)^-1 (seed 5), and white-noise grid fields N(0,1) of N_theta x N_phi
 points (seed 6) standing in for the stochastic component, which is not

@@ -19,3 +19,10 @@ def orc():
 
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def sht_orc():
+    from oracle import sht
+
+    return sht

@@ -88,3 +88,34 @@ def test_default_opts():
     o = M.mpchol_default_opts()
     assert o.band == 1 and o.allowed == 0xF and o.lo16 == M.LO16_F16 and o.verify_eps == 1e-9
     assert o.lo32 == M.LO32_BF16X3
+
+
+def test_sht_argument_checks_before_any_device_call():
+    import paper_2408_04440_amd.mpchol as M
+
+    L = M.lib()
+    s = C.c_void_p()
+    bad = [(0, 2, 1, 1), (10, 10, 20, 4), (10, 11, 18, 4), (10, 11, 19, 4), (7, 8, 15, 4), (8, 9, 15, 0),
+           (1025, 1026, 2050, 1), (300, 301, 4200, 1)]
+    for Lb, nth, nph, tmax in bad:
+        assert L.mpchol_sht_create(C.byref(s), Lb, nth, nph, tmax, 0, None) == M.EINVAL, (Lb, nth, nph, tmax)
+        assert not s.value
+    assert b"2, 3 and 5" in L.mpchol_sht_last_error()  # the last case: 4200 > 4096 and 4200 = 2^3 3 5^2 7
+    assert L.mpchol_sht_create(None, 8, 9, 15, 1, 0, None) == M.EINVAL
+    assert L.mpchol_sht_forward(None, None, 1, None) == M.EINVAL
+    assert L.mpchol_sht_inverse(None, None, 1, None) == M.EINVAL
+    assert L.mpchol_sht_info(None, None, None, None) == M.EINVAL
+    assert L.mpchol_sht_destroy(None) == 0
+
+
+def test_sht_binding_checks_shapes():
+    import torch
+
+    import paper_2408_04440_amd.mpchol as M
+
+    with pytest.raises(ValueError):
+        M.mpchol_sht_forward(C.c_void_p(1), torch.zeros((2, 9, 15), dtype=torch.float64),
+                             torch.zeros((2, 63), dtype=torch.float64), 8)
+    with pytest.raises(ValueError):
+        M.mpchol_sht_inverse(C.c_void_p(1), torch.zeros((2, 64), dtype=torch.float64),
+                             torch.zeros((3, 9, 15), dtype=torch.float64), 8)

@@ -150,6 +150,23 @@ def test_grid_too_small_is_rejected():
         sht.sht_forward(np.zeros((6, 8)), 5)   # N_phi < 2L - 1
 
 
+def test_pole_reading_only_drops_odd_orders_at_the_poles():
+    """Odd-order longitude content added to the two pole rows changes
+    nothing (those samples are taken as zero); even-order content does."""
+    L, nt, nph = 7, 9, 14
+    rng = np.random.default_rng(11)
+    Z = rng.standard_normal((nt, nph))
+    base = sht.sht_forward(Z, L)
+    _, ph = sht.grid(nt, nph)
+    Zo = Z.copy()
+    Zo[0] += 0.7 * np.cos(3 * ph) - 0.2 * np.sin(ph)
+    Zo[-1] += 0.4 * np.sin(5 * ph)
+    assert np.abs(sht.sht_forward(Zo, L) - base).max() <= 1e-14
+    Ze = Z.copy()
+    Ze[0] += 0.5 * np.cos(2 * ph)
+    assert np.abs(sht.sht_forward(Ze, L) - base).max() > 1e-3
+
+
 def test_odd_q_terms_cancel():
     """The q = +-1 terms of I contribute nothing: K_{m,-m'} = (-1)^m K_{m,m'}
     and S_{l,m,-m''} = (-1)^m S_{l,m,m''} pair each (m', m'') term with a
