@@ -123,6 +123,68 @@ def cpu_baseline(sigma, x, rho, nugget, target_s=15.0):
                       f"({t:.2f} s, info={info})"}, ld_ref
 
 
+def bench_sht(M, torch, L, T, reps, cpu):
+    """Forward and inverse SHT of T band-limited fields (inverse of N(0,1)/(1+l)
+    coefficients, generated on the device) on the L+1 x 2L grid, timed with
+    events on the transform's stream; per-field rates and the whole-call
+    rooflines (algorithmic HBM bytes: the field and its coefficients once;
+    FP64 GEMM flops of the folded tables)."""
+    import synth
+
+    nth, nph = L + 1, 2 * L
+    st = torch.cuda.current_stream()
+    s = M.mpchol_sht_create(L, nth, nph, T, stream=st)
+    try:
+        info = M.mpchol_sht_info(s)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(synth.SEED_SHT_COEFFS)
+        f = torch.randn((T, L * L), dtype=torch.float64, device="cuda", generator=g)
+        f *= torch.tensor(1.0 / (1.0 + synth.sh_degrees(L)), device="cuda")
+        Z = torch.empty((T, nth, nph), dtype=torch.float64, device="cuda")
+        f2 = torch.empty_like(f)
+        M.mpchol_sht_inverse(s, f, Z, L)
+        M.mpchol_sht_forward(s, Z, f2, L)
+        torch.cuda.synchronize()
+        rt = ((f2 - f).abs().max() / f.abs().max()).item()
+        times = {}
+        for name, fn in (("forward", lambda: M.mpchol_sht_forward(s, Z, f2, L)),
+                         ("inverse", lambda: M.mpchol_sht_inverse(s, f, Z, L))):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(st)
+            for _ in range(reps):
+                fn()
+            ev[1].record(st)
+            ev[1].synchronize()
+            times[name] = ev[0].elapsed_time(ev[1]) / reps
+    finally:
+        M.mpchol_sht_destroy(s)
+    field_b, coef_b = nth * nph * 8, L * L * 8
+    out = {"L": L, "grid": [nth, nph], "batch": T, "round_trip_rel_err": rt,
+           "table_bytes": info["table_bytes"], "work_bytes": info["work_bytes"]}
+    for name in ("forward", "inverse"):
+        ms = times[name]
+        out[name] = {"ms_per_call": round(ms, 3), "us_per_field": round(ms * 1e3 / T, 3),
+                     "fields_per_s": round(T / ms * 1e3, 1),
+                     "hbm_gbs_algorithmic": round((field_b + coef_b) * T / ms / 1e6, 1),
+                     "gemm_tflops": round(info["gemm_flops_per_step"] * T / ms / 1e9, 2)}
+    if cpu:
+        import oracle.sht as osht  # CPU leg only
+
+        from threadpoolctl import threadpool_limits
+
+        D = osht.wigner_table(L)
+        Zs = synth.sht_fields(2, nth, nph)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for t in range(2):
+                osht.sht_forward_real(Zs[t], L, D)
+            tc = (time.perf_counter() - t0) / 2
+        out["cpu_baseline"] = {"value": round(1.0 / tc, 4), "unit": "fields/s", "cores": 1, "kind": "oracle",
+                               "sample": f"oracle forward SHT (numpy FFT + Wigner-d sums) of 2 white-noise fields "
+                                         f"at L={L} ({tc:.2f} s per field, Wigner table excluded)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +206,12 @@ def main():
                     "each with its backward error (e.g. norm,learned)")
     ap.add_argument("--producer", type=int, default=0, metavar="M",
                     help="also time the covariance producer (Sigma = Xi Xi^T / M + nugget I) for M samples")
+    ap.add_argument("--sht", type=int, default=0, metavar="L",
+                    help="also time the spherical harmonic transform and its inverse at band limit L "
+                         "(grid L+1 x 2L) on a batch of --sht-batch fields")
+    ap.add_argument("--sht-batch", type=int, default=0, metavar="T",
+                    help="fields per SHT call (default 512 at L <= 400, else 128)")
+    ap.add_argument("--sht-only", action="store_true", help="skip the factorization; time only the SHT")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB megabytes first (counter calibration)")
     args = ap.parse_args()
@@ -158,6 +226,16 @@ def main():
 
     import synth
     import paper_2408_04440_amd.mpchol as M
+
+    sht_T = args.sht_batch or (512 if args.sht <= 400 else 128)
+    if args.sht_only:
+        Ls = args.sht or 360
+        sht = bench_sht(M, torch, Ls, sht_T, max(args.steps, 1), not args.no_cpu)
+        log(f"  sht: {sht}")
+        print(json.dumps({"metric": f"SHT fields/s (forward), L={Ls}", "value": sht["forward"]["fields_per_s"],
+                          "unit": "fields/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+                          "dtype": "f64", "data": "synthetic", "sht": sht}), flush=True)
+        return
 
     cfg = CONFIGS[args.config]
     L, tile, rho, eps = cfg["L"], cfg["tile"], cfg["rho"], cfg["eps"]
@@ -311,6 +389,10 @@ def main():
         log(f"  producer: {producer}")
         del Xs
     M.mpchol_destroy(h)
+    sht = None
+    if args.sht > 0:
+        sht = bench_sht(M, torch, args.sht, sht_T, max(args.steps, 1), False)
+        log(f"  sht: {sht}")
 
     cpu, ld_ref = (None, None)
     if not args.no_cpu:
@@ -338,6 +420,7 @@ def main():
         "verify_first": verify_value(st["verify_first"]),
         "compare": compare or None,
         "producer": producer,
+        "sht": sht,
         "backward_error": berr,
         "logdet_rel_err": None if ld_ref is None else abs(ld - ld_ref) / abs(ld_ref),
         "solve_backward_error": solve_be,
