@@ -309,11 +309,13 @@ int mpchol_mlp_predict(mpchol_mlp_t m, const float *X, int64_t nb, float *logits
 typedef struct mpchol_sht *mpchol_sht_t;
 
 /* Create a transform object on `device`, ordered on `stream` (NULL: the
- * default stream): computes d^l_{k,m}(pi/2) (recursion in the first index),
- * the forward and inverse tables (about L^3 / 2 doubles each) and work
+ * default stream): computes d^l_{k,m}(pi/2) (recursion in the first index)
+ * and from it, once, the composition of every step after the longitude FFT
+ * (colatitude DFT of the extended G_m and both sums) as one table per order
+ * for each direction (about L^2 N_theta / 4 doubles each), and work
  * buffers for up to tmax time steps per call.  Requires 1 <= L <= 1024,
- * N_theta > L, N_phi >= 2L - 1, N_phi and 2 N_theta - 2 products of 2, 3 and 5
- * of at most 4096, 1 <= tmax <= 2^20.  Errors: MPCHOL_EINVAL (sizes, with a
+ * N_theta > L, N_phi >= 2L - 1, N_phi a product of 2, 3 and 5 of at most 4096,
+ * 1 <= tmax <= 2^20.  Errors: MPCHOL_EINVAL (sizes, with a
  * message from mpchol_sht_last_error), MPCHOL_ENOMEM, MPCHOL_EHIP.
  * Synchronizes the stream once. */
 int mpchol_sht_create(mpchol_sht_t *s, int32_t L, int32_t ntheta, int32_t nphi, int32_t tmax, int32_t device,

@@ -95,7 +95,7 @@ def test_sht_argument_checks_before_any_device_call():
 
     L = M.lib()
     s = C.c_void_p()
-    bad = [(0, 2, 1, 1), (10, 10, 20, 4), (10, 11, 18, 4), (10, 11, 19, 4), (7, 8, 15, 4), (8, 9, 15, 0),
+    bad = [(0, 2, 1, 1), (10, 10, 20, 4), (10, 11, 18, 4), (10, 11, 19, 4), (7, 8, 14, 4), (8, 9, 15, 0),
            (1025, 1026, 2050, 1), (300, 301, 4200, 1)]
     for Lb, nth, nph, tmax in bad:
         assert L.mpchol_sht_create(C.byref(s), Lb, nth, nph, tmax, 0, None) == M.EINVAL, (Lb, nth, nph, tmax)
