@@ -69,7 +69,6 @@ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x +
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 // multiply by i^e, e in 0..3
 __device__ inline double2 ipow(double2 a, int e)
 {
@@ -794,7 +793,7 @@ int mpchol_sht_create(mpchol_sht_t *out, int32_t L, int32_t ntheta, int32_t nphi
     h->vrows = rup64(h->H, GBM);
     h->gblk = (int64_t)h->kph * h->ldb;
     h->oblk = h->vrows * h->ldb;
-    const int H = h->H, M = 2 * ntheta - 2;
+    const int H = h->H;
 
     // block geometry per (m, p): degrees l = lstart(m,p) + 2r, r < R
     const int nb = 2 * L;
@@ -919,7 +918,6 @@ int mpchol_sht_create(mpchol_sht_t *out, int32_t L, int32_t ntheta, int32_t nphi
         mpchol_sht_destroy(h);
         return MPCHOL_EHIP;
     }
-    (void)M;
     set_smem_attr((const void *)phi_forward_kernel, fft_smem(nphi, h->nseq));
     set_smem_attr((const void *)phi_inverse_kernel, fft_smem(nphi, h->nseq));
     set_smem_attr((const void *)gemm_forward_kernel, GS::SMEM);
