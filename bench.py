@@ -403,8 +403,8 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if rule == M.RULE_FP64 else "f64/f32/" + ("bf16" if cfg["lo16"] else "f16") +
-                 ("/fp8-e4m3" if cfg["allowed"] & 8 else ""),
+        "dtype": "f64" if rule == M.RULE_FP64 else "f64/" + ("bf16x3-f32acc" if args.lo32 == "bf16x3" else "f32") + "/" +
+                 ("bf16" if cfg["lo16"] else "f16") + ("/fp8-e4m3" if cfg["allowed"] & 8 else ""),
         "data": "synthetic",
         "config": {"workload": f"SH covariance L={L} (N={n}), tile {tile}, rho={rho}, nugget 1e-8, "
                                f"{[k for k, v in RULES.items() if v == rule][0]} rule eps={eps}, classes {cfg['label']}",
