@@ -206,9 +206,9 @@ def main():
                     "each with its backward error (e.g. norm,learned)")
     ap.add_argument("--producer", type=int, default=0, metavar="M",
                     help="also time the covariance producer (Sigma = Xi Xi^T / M + nugget I) for M samples")
-    ap.add_argument("--sht", type=int, default=0, metavar="L",
+    ap.add_argument("--sht", type=int, default=None, metavar="L",
                     help="also time the spherical harmonic transform and its inverse at band limit L "
-                         "(grid L+1 x 2L) on a batch of --sht-batch fields")
+                         "(grid L+1 x 2L) on a batch of --sht-batch fields (default 360 with --config c4, 0 = off)")
     ap.add_argument("--sht-batch", type=int, default=0, metavar="T",
                     help="fields per SHT call (default 512 at L <= 400, else 128)")
     ap.add_argument("--sht-only", action="store_true", help="skip the factorization; time only the SHT")
@@ -217,6 +217,8 @@ def main():
     args = ap.parse_args()
     if args.compare is None:  # the learned selector beside the norm rule on the mixed workloads
         args.compare = "learned" if args.config in ("c4", "c5") and args.rule in (None, "norm") else ""
+    if args.sht is None:  # the transform of the same band limit beside the default workload
+        args.sht = 360 if args.config == "c4" and not args.sht_only else 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
