@@ -201,7 +201,8 @@ def main():
     ap.add_argument("--band-variant", type=int, default=None, choices=[1, 2, 3],
                     help="band rule variant: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP")
     ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
-                    help="precision map of the timed steps (default: norm, or fp64 for FP64-only workloads)")
+                    help="precision map of the timed steps (default: learned for the four-class workloads c4/c5, "
+                         "norm for c3, fp64 for FP64-only workloads)")
     ap.add_argument("--compare", default=None, help="comma list of extra rules timed once after the steps, "
                     "each with its backward error (e.g. norm,learned)")
     ap.add_argument("--producer", type=int, default=0, metavar="M",
@@ -215,8 +216,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="run one plain device copy of MB megabytes first (counter calibration)")
     args = ap.parse_args()
-    if args.compare is None:  # the learned selector beside the norm rule on the mixed workloads
-        args.compare = "learned" if args.config in ("c4", "c5") and args.rule in (None, "norm") else ""
+    # the path's precision choice on the four-class workloads is the learned selector
+    # (MLP map, randomized backward-error check, norm-rule fallback); the norm rule
+    # alone is timed beside it
+    if args.rule is None and args.config in ("c4", "c5"):
+        args.rule = "learned"
+    if args.compare is None:
+        args.compare = {"learned": "norm", "norm": "learned"}.get(args.rule, "") if args.config in ("c4", "c5") else ""
     if args.sht is None:  # the transform of the same band limit beside the default workload
         args.sht = 360 if args.config == "c4" and not args.sht_only else 0
     if args.gpus != 1:
