@@ -133,7 +133,7 @@ int mpchol_set_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_devic
  * sigma and x: host arrays of n doubles; rho > 0; nugget >= 0. */
 int mpchol_set_generator(mpchol_t h, const double *sigma, const double *x, double rho, double nugget);
 
-/* Use the covariance estimated from samples (Sec. III, "Modeling the Temporal
+/* Use the covariance estimated from samples (Sec. III.A.3, "Modeling the Temporal
  * Dependence and Constructing a Covariance Matrix": the average of the outer
  * products of the R(T-P) residual vectors, with a small diagonal perturbation
  * when there are fewer samples than L^2):

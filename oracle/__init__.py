@@ -122,7 +122,7 @@ def cov_dense(sigma, x, rho, nugget):
 
 def cov_samples(xi, scale, nugget):
     """S = scale * xi xi^T + nugget I for samples xi (n x m): the covariance
-    estimator of the residual vectors (Sec. III, constructing the covariance
+    estimator of the residual vectors (Sec. III.A.3, constructing the covariance
     matrix)."""
     xi = _fortran(xi)
     n, m = xi.shape

@@ -56,7 +56,7 @@ void orc_cov_dense(int64_t n, const double *sigma, const double *x, double rho, 
 
 /* ------------------------------------------------------------------------
  * Covariance from samples (the estimator of the residual covariance in Sec.
- * III, "Modeling the Temporal Dependence and Constructing a Covariance
+ * III.A.3, "Modeling the Temporal Dependence and Constructing a Covariance
  * Matrix": the average of the outer products of the R(T-P) residual vectors,
  * plus a small diagonal perturbation when there are fewer samples than L^2):
  *   S_ij = scale * sum_k xi_ik xi_jk + nugget * delta_ij,

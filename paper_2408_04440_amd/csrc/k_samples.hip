@@ -1,5 +1,5 @@
 // Covariance from samples: Sigma = scale * Xi Xi^T + nugget I, the estimator
-// of the residual covariance (Sec. III, "Modeling the Temporal Dependence and
+// of the residual covariance (Sec. III.A.3, "Modeling the Temporal Dependence and
 // Constructing a Covariance Matrix": the average of the R(T-P) outer products
 // of the residual vectors, plus a small diagonal perturbation when there are
 // fewer samples than L^2).  A tall-skinny SYRK on the FP64 MFMA: every lower
