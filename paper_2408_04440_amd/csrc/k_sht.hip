@@ -40,7 +40,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/mpchol.h"
@@ -729,8 +731,21 @@ template <typename T> int upload(T *d, const std::vector<T> &h, hipStream_t st)
 
 size_t fft_smem(int n, int nseq) { return (size_t)(nseq + 1) * n * sizeof(double2); }
 
+// Raise a kernel's dynamic-LDS limit to at least `bytes` (never lower it: an
+// object created earlier with larger transforms keeps launching).
 void set_smem_attr(const void *k, size_t bytes)
 {
+    static std::vector<std::pair<const void *, size_t>> seen;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    for (auto &e : seen)
+        if (e.first == k) {
+            if (bytes <= e.second) return;
+            e.second = bytes;
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            return;
+        }
+    seen.emplace_back(k, bytes);
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 

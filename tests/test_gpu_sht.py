@@ -160,3 +160,30 @@ def test_batch_limits_and_empty_batch():
         assert L_.mpchol_sht_forward(s, None, 2, C.c_void_p(f.data_ptr())) == mod.EINVAL
     finally:
         mod.mpchol_sht_destroy(s)
+
+
+def test_large_object_still_runs_after_a_smaller_one_is_created():
+    """Kernel launch limits set for a small object must not break an object
+    created earlier with longer transforms (69 KB of LDS per workgroup at
+    N_phi = 720)."""
+    torch = torch_cuda()
+    mod = M()
+    L, nth, nph, T = 360, 361, 720, 4
+    big = mod.mpchol_sht_create(L, nth, nph, T)
+    small = mod.mpchol_sht_create(8, 9, 15, 2)
+    try:
+        f = torch.tensor(synth.sht_coeffs(L, T), device="cuda")
+        Z = torch.empty((T, nth, nph), dtype=torch.float64, device="cuda")
+        f2 = torch.empty_like(f)
+        mod.mpchol_sht_inverse(big, f, Z, L)
+        mod.mpchol_sht_forward(big, Z, f2, L)
+        fs = torch.tensor(synth.sht_coeffs(8, 2), device="cuda")
+        Zs = torch.empty((2, 9, 15), dtype=torch.float64, device="cuda")
+        mod.mpchol_sht_inverse(small, fs, Zs, 8)
+        torch.cuda.synchronize()
+        rt = ((f2 - f).abs().max() / f.abs().max()).item()
+        log(f"  round trip after a second object: {rt:.2e}")
+        assert rt <= 1e-11
+    finally:
+        mod.mpchol_sht_destroy(small)
+        mod.mpchol_sht_destroy(big)
