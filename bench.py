@@ -47,13 +47,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-UPDATE_SOURCES = ["paper_2408_04440_amd/csrc/gemm_core.h", "paper_2408_04440_amd/csrc/k_factor.hip"]
+UPDATE_SOURCES = ["paper_2408_04440_amd/csrc/gemm_core.h", "paper_2408_04440_amd/csrc/k_factor.hip",
+                  "paper_2408_04440_amd/build.py"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_c4.json")
 
 
 def update_kernel_hash():
-    """Hash of the update kernels' sources: counter-based traffic numbers are
-    only reported while the kernels are the ones they were measured on."""
+    """Hash of the update kernels' sources and build flags: counter-based
+    traffic numbers are only reported while the kernels are the ones they were
+    measured on."""
     import hashlib
 
     h = hashlib.sha256()
