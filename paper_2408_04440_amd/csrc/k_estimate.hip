@@ -211,12 +211,14 @@ __global__ __launch_bounds__(256) void lt_apply_kernel(Tiles T, const double *V,
 
 // Z[rows r0.. of tile row I] = sum_{K <= I} L_IK(r0:r0+64, :) W[rows of K]:
 // block per (I, 64-row strip), K dimension = the columns of L_IK, ER at a time.
+// The last tile rows, with the most tiles to walk, take the first blocks so
+// that the longest blocks start first.
 __global__ __launch_bounds__(256) void l_apply_kernel(Tiles T, const double *W, int64_t ldw, double *Z)
 {
     __shared__ double ls[ER][EB + 1];  // ls[c][r] = L_IK(r0 + r, c0 + c)
     __shared__ double ws[ER][EK + 1];  // ws[c][q] = W[K*b + c0 + c, q]
     const int b = T.b, per = b / EB;
-    const int I = blockIdx.x / per, r0 = (blockIdx.x % per) * EB;
+    const int I = T.nt - 1 - (int)(blockIdx.x / per), r0 = (blockIdx.x % per) * EB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % 2, wn = wave / 2, gi = lane & 15, gg = lane >> 4;
     double4_t acc[2][2];
