@@ -71,7 +71,8 @@ void launch_normal_matrix(uint64_t seed, int64_t n, int ndraws, float *Z, int64_
 // One 128 x 128 block of Y per workgroup of 16 waves (32 x 32 each): rows of
 // tile row I, columns of draws; sum over K <= I of L_IK Z_K with FP32 MFMA,
 // each stored tile widened (exactly, or rounded to FP32 for FP64 tiles) on its
-// way into LDS.
+// way into LDS.  The last tile rows, with the most tiles to walk, take the
+// first blocks.
 constexpr int SB = 128, SK = 16, SLD = SB + 4, SW = 4, SNT = 64 * SW * SW, SPER = SK * SB / SNT;
 
 __global__ __launch_bounds__(SNT) void lower_apply_kernel(Tiles T, const float *Z, int64_t ldz, float *Y, int64_t ldy,
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(SNT) void lower_apply_kernel(Tiles T, const float *
 {
     __shared__ float As[2][SK][SLD], Bs[2][SK][SLD];
     const int b = T.b, nsub = b / SB;
-    const int I = blockIdx.x / nsub, tm = blockIdx.x % nsub;
+    const int I = T.nt - 1 - (int)(blockIdx.x / nsub), tm = blockIdx.x % nsub;
     const int s0 = blockIdx.y * SB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % SW, wn = wave / SW, gi = lane & 15, gg = lane >> 4;
