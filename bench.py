@@ -228,8 +228,8 @@ def main():
     if args.sht is None:  # the transform of the same band limit beside the default workload
         args.sht = 360 if args.config == "c4" and not args.sht_only else 0
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
+        print(f"bench.py: the factorization runs on one GPU (asked for --gpus {args.gpus}); "
+              "its decomposition over several GPUs is designed, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
