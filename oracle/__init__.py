@@ -83,6 +83,7 @@ def lib():
         L.orc_tile_norms.restype = d
         L.orc_tile_norms.argtypes = [i64, i64, dp, i64, dp, dp]
         L.orc_map_norm.argtypes = [i64, dp, d, d, i32, C.c_uint, i32, C.POINTER(C.c_uint8)]
+        L.orc_map_band.argtypes = [i64, i32, i32, C.c_uint, C.POINTER(C.c_uint8)]
         L.orc_mp_factor.restype = i64
         L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32, i32]
         L.orc_split3.restype = C.c_float
@@ -253,6 +254,13 @@ def map_norm(fro2, total, eps, band=1, allowed=0xF, lo16=F16):
     fro2 = _fortran(fro2)
     out = np.zeros((nt, nt), dtype=np.uint8, order="F")
     lib().orc_map_norm(nt, _dp(fro2), total, eps, band, allowed, lo16, out.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return out
+
+
+def map_band(nt, band=1, variant=3, allowed=0xF):
+    """Band rule map (Sec. IV.B variants: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP), nt x nt uint8."""
+    out = np.zeros((nt, nt), dtype=np.uint8, order="F")
+    lib().orc_map_band(int(nt), int(band), int(variant), int(allowed), out.ctypes.data_as(C.POINTER(C.c_uint8)))
     return out
 
 

@@ -451,6 +451,41 @@ void orc_map_norm(int64_t nt, const double *fro2, double total_fro, double eps, 
         }
 }
 
+/* Band rule (Sec. IV.B's precision variants DP/SP, DP/SP/HP and DP/HP; the
+ * band-based mixed precision of Sec. III.D).  Tiles with I - J <= band (the
+ * diagonal included) are FP64.  variant 1 (DP/SP): every other lower tile
+ * FP32; variant 3 (DP/HP): every other lower tile 16-bit; variant 2
+ * (DP/SP/HP): tiles with band < I - J <= w32 FP32 and the rest 16-bit, where
+ * w32 is the smallest width whose FP32 band holds at least 5% of the
+ * nt(nt-1)/2 strict-lower tiles (every off-band tile when no width reaches
+ * it).  A class outside `allowed` is raised to the nearest more precise
+ * allowed class (FP64 is always allowed).  The 5% count visits the tiles
+ * one by one. */
+void orc_map_band(int64_t nt, int band, int variant, unsigned allowed, uint8_t *map)
+{
+    const double total = (double)nt * (double)(nt - 1) / 2.0;
+    int64_t w32 = band;
+    if (variant == 2)
+        for (w32 = band; w32 < nt - 1; ++w32) {
+            int64_t cnt = 0;
+            for (int64_t J = 0; J < nt; ++J)
+                for (int64_t I = J + 1; I < nt; ++I)
+                    if (I - J > band && I - J <= w32) ++cnt;
+            if ((double)cnt >= 0.05 * total) break;
+        }
+    for (int64_t J = 0; J < nt; ++J)
+        for (int64_t I = 0; I < nt; ++I) {
+            int c = ORC_P64;
+            if (I > J && I - J > band) {
+                if (variant == 1) c = ORC_P32;
+                else if (variant == 2) c = (I - J <= w32) ? ORC_P32 : ORC_P16;
+                else c = ORC_P16;
+                while (c > ORC_P64 && !(allowed & (1u << c))) --c;
+            }
+            map[I + J * nt] = (I >= J) ? (uint8_t)c : 0;
+        }
+}
+
 /* ------------------------------------------------------------------------
  * O2: the mixed-precision tile Cholesky replayed on the CPU with explicit
  * rounding (Sec. III.D with the task graph and sender-side conversion of
@@ -508,6 +543,11 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
     /* panel copies per consumer class: values (scaled for 16-bit/FP8) */
     double *C[4];
     for (int c = 0; c < 4; ++c) C[c] = malloc(sizeof(double) * (size_t)np * b);
+    /* with lo32: the three BF16 parts of each FP32 copy, made once per panel
+     * tile at conversion (the same values orc_split3 gives at every use) */
+    float *S3[3] = {NULL, NULL, NULL};
+    if (lo32)
+        for (int p = 0; p < 3; ++p) S3[p] = malloc(sizeof(float) * (size_t)np * b);
     int *tq = malloc(sizeof(int) * nt * 4);
     int64_t info = 0;
 
@@ -588,6 +628,8 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                         else if (q == ORC_P32) cv = (double)(float)v;
                         else cv = orc_round((double)(float)ldexp(v, t), fmt);
                         C[q][(i0 + r) + (size_t)c * np] = cv;
+                        if (q == ORC_P32 && lo32)
+                            for (int p = 0; p < 3; ++p) S3[p][(i0 + r) + (size_t)c * np] = orc_split3(cv, p);
                     }
             }
         }
@@ -618,9 +660,9 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                         for (int t = 0; t < 6; ++t)
                             for (int64_t cc = 0; cc < b; ++cc) {
                                 int64_t c = order ? b - 1 - cc : cc;
-                                float bj = orc_split3(CJ[(j0 + s) + (size_t)c * np], pb[t]);
-                                const double *ci = CI + i0 + (size_t)c * np;
-                                for (int64_t r = 0; r < b; ++r) acc32[r] += orc_split3(ci[r], pa[t]) * bj;
+                                float bj = S3[pb[t]][(j0 + s) + (size_t)c * np];
+                                const float *ci = S3[pa[t]] + i0 + (size_t)c * np;
+                                for (int64_t r = 0; r < b; ++r) acc32[r] += ci[r] * bj;
                             }
                         for (int64_t r = 0; r < b; ++r) {
                             float w = (float)W[IDX(i0 + r, j0 + s)];
@@ -649,6 +691,7 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < n; ++i) Lhat[i + j * ldl] = (i >= j) ? W[IDX(i, j)] : 0.0;
     for (int c = 0; c < 4; ++c) free(C[c]);
+    for (int p = 0; p < 3; ++p) free(S3[p]);
     free(tq);
     free(W);
     return info;

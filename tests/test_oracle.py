@@ -516,3 +516,269 @@ def test_mp_factor_split_close_to_fp32(orc):
     d_oo = np.linalg.norm(L0 - L1) / np.linalg.norm(L0)
     d_so = np.linalg.norm(Ls - L0) / np.linalg.norm(L0)
     assert 0 < d_so <= 4.0 * d_oo
+
+
+# ---------------------------------------------------------------- Adam against hand-derived steps
+def test_adam_two_steps_golden(orc):
+    """Two Adam steps (Kingma & Ba, with bias correction) against values derived
+    by hand in exact rational arithmetic (tests/golden/adam_two_steps.txt).
+    eps = 0.5 makes the bias correction and the place of eps visible in every
+    step-1 value."""
+    rows = [l.split() for l in open(os.path.join(GOLD, "adam_two_steps.txt")) if l.strip() and not l.startswith("#")]
+    th0 = np.array([float(r[1]) for r in rows])
+    g1 = np.array([float(r[2]) for r in rows])
+    g2 = np.array([float(r[3]) for r in rows])
+    want1 = np.array([float(r[4]) for r in rows])
+    want2 = np.array([float(r[5]) for r in rows])
+    P, m, v = th0.copy(), np.zeros(3), np.zeros(3)
+    orc.adam_step(P, g1, m, v, 1, lr=0.1, b1=0.5, b2=0.75, eps=0.5)
+    assert np.allclose(P, want1, rtol=2e-16, atol=0)
+    orc.adam_step(P, g2, m, v, 2, lr=0.1, b1=0.5, b2=0.75, eps=0.5)
+    assert np.allclose(P, want2, rtol=4e-16, atol=0)
+
+
+# ---------------------------------------------------------------- per-tile residual attribution
+@pytest.mark.parametrize("I,J", [(0, 0), (2, 1), (4, 0), (4, 4), (3, 3)])
+def test_tile_residual2_planted_in_one_tile(orc, I, J):
+    """A = L0 L0^T exactly (small integers) plus an integer perturbation E
+    planted in the lower part of tile (I, J) only: the per-tile residual of L0
+    is exactly the planted tile's ||E||^2 (strict-lower entries of a diagonal
+    tile counted twice, as in the symmetric matrix) and exactly zero in every
+    other tile.  n = 70, b = 16: the last tile row and column have 6 entries."""
+    n, b = 70, 16
+    nt = (n + b - 1) // b
+    L0 = synth.int_lower(n, 31)
+    A = L0 @ L0.T
+    E = np.zeros((n, n))
+    r0, r1 = I * b, min(n, (I + 1) * b)
+    c0, c1 = J * b, min(n, (J + 1) * b)
+    vals = np.round(synth.normal(40 + 7 * I + J, (r1 - r0) * (c1 - c0)) * 2).reshape(r1 - r0, c1 - c0)
+    vals[vals == 0] = 1.0
+    E[r0:r1, c0:c1] = vals
+    if I == J:
+        E = np.tril(E)
+        E = E + np.tril(E, -1).T  # symmetric, so the planted matrix stays a covariance
+    t2 = orc.tile_residual2(A + E, L0, b)
+    want = np.zeros((nt, nt))
+    blk = np.tril(E[r0:r1, c0:c1]) if I == J else E[r0:r1, c0:c1]
+    w = np.where(np.eye(r1 - r0, c1 - c0, dtype=bool), 1.0, 2.0) if I == J else 1.0
+    want[I, J] = np.sum(w * blk * blk)
+    assert np.array_equal(np.tril(t2), want)
+
+
+# ---------------------------------------------------------------- O2 rounding placement
+_E4M3 = None
+
+
+def _e4m3_table():
+    """Every finite non-negative E4M3FN value, indexed by its code, decoded from
+    the OCP bit definition (4 exponent bits, bias 7, 3 mantissa bits, no infinity,
+    code 0x7F is NaN)."""
+    global _E4M3
+    if _E4M3 is None:
+        t = []
+        for c in range(0x7F):
+            e, m = c >> 3, c & 7
+            t.append(m / 8 * 2.0 ** -6 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7))
+        _E4M3 = np.array(t)
+    return _E4M3
+
+
+def _rne_e4m3(x):
+    """Nearest E4M3FN value of the float x, ties to the even code, saturating at 448."""
+    tab = _e4m3_table()
+    a = min(abs(float(x)), 448.0)
+    d = np.abs(tab - a)
+    best = np.flatnonzero(d == d.min())
+    code = best[0] if len(best) == 1 else [c for c in best if c % 2 == 0][0]
+    return float(np.copysign(tab[code], x))
+
+
+def _rne_bf16(x):
+    """float32 x to bfloat16 by round-to-nearest-even on the 16 dropped bits of its encoding."""
+    u = int(np.array(x, dtype=np.float32).view(np.uint32))
+    low, high = u & 0xFFFF, u >> 16
+    if low > 0x8000 or (low == 0x8000 and high & 1):
+        high += 1
+    return float(np.array(high << 16, dtype=np.uint32).view(np.float32))
+
+
+def _scale(amax, maxf):
+    """Largest integer t with amax * 2^t <= maxf (0 for amax = 0)."""
+    if amax == 0.0:
+        return 0
+    t = 0
+    while amax * 2.0 ** t > maxf:
+        t -= 1
+    while amax * 2.0 ** (t + 1) <= maxf:
+        t += 1
+    return t
+
+
+def _o2_replica(A, b, cmap, lo16, lo32):
+    """The mixed tile algorithm written out step by step for tiny sizes, with
+    rounding by numpy's float32/float16 casts, bfloat16 from the float32
+    encoding and E4M3 from its code table: W in FP64 with FP32 work tiles for
+    lower classes; POTRF in FP64; TRSM in FP64 then rounded to FP32 (lower
+    classes) and stored as fmt(f32(v 2^t)) 2^-t (16-bit/FP8); one copy per
+    consumer class made from the stored tile; GEMMs in the tile's class with
+    float products and float sums in k order, the FP32 work tile updated in
+    float.  f32 = np.float32, so every rounding placement is explicit."""
+    f32 = lambda v: float(np.float32(v))
+    n = A.shape[0]
+    nt = -(-n // b)
+    npd = nt * b
+    W = np.eye(npd)
+    W[:n, :n] = A
+    for I in range(nt):
+        for J in range(I):
+            if cmap[I, J] != 0:
+                W[I * b:(I + 1) * b, J * b:(J + 1) * b] = np.float32(W[I * b:(I + 1) * b, J * b:(J + 1) * b])
+
+    def fmt_round(v, q):
+        if q == 2 and lo16 == 2:
+            return _rne_bf16(v)
+        if q == 2:
+            return float(np.float16(np.float32(v)))
+        return _rne_e4m3(v)
+
+    def maxf(q):
+        return None if (q == 2 and lo16 == 2) else (65504.0 if q == 2 else 448.0)
+
+    tsc = np.zeros((nt, nt), np.int32)
+    for k in range(nt):
+        k0 = k * b
+        D = W[k0:k0 + b, k0:k0 + b]
+        for c in range(b):  # POTRF, right-looking
+            D[c, c] = np.sqrt(D[c, c])
+            for i in range(c + 1, b):
+                D[i, c] /= D[c, c]
+            for j in range(c + 1, b):
+                for i in range(j, b):
+                    D[i, j] -= D[i, c] * D[j, c]
+        copies = {}
+        for I in range(k + 1, nt):
+            X = W[I * b:(I + 1) * b, k0:k0 + b]
+            for c in range(b):  # TRSM, forward substitution in FP64
+                for cc in range(c):
+                    X[:, c] -= X[:, cc] * D[c, cc]
+                X[:, c] /= D[c, c]
+            q = cmap[I, k]
+            if q != 0:
+                X[:] = np.float32(X)
+                if maxf(q) is not None or q == 2:
+                    t = _scale(np.max(np.abs(X)), maxf(q)) if maxf(q) else 0
+                    if q >= 2:
+                        tsc[I, k] = t
+                        for r in range(b):
+                            for c in range(b):
+                                X[r, c] = fmt_round(f32(X[r, c] * 2.0 ** t), q) * 2.0 ** -t
+            m = np.max(np.abs(X))
+            cp = {0: (X.copy(), 0), 1: (np.float32(X).astype(np.float64), 0)}
+            for q in (2, 3):
+                t = _scale(m, maxf(q)) if maxf(q) else 0
+                cp[q] = (np.array([[fmt_round(f32(X[r, c] * 2.0 ** t), q) for c in range(b)] for r in range(b)]), t)
+            copies[I] = cp
+        for I in range(k + 1, nt):
+            for J in range(k + 1, I + 1):
+                q = 0 if I == J else cmap[I, J]
+                (CI, tI), (CJ, tJ) = copies[I][q], copies[J][q]
+                Wt = W[I * b:(I + 1) * b, J * b:(J + 1) * b]
+                for r in range(b):
+                    for s in range(b):
+                        if q == 0:
+                            acc = 0.0
+                            for c in range(b):
+                                acc += CI[r, c] * CJ[s, c]
+                            Wt[r, s] -= acc
+                            continue
+                        acc = np.float32(0.0)
+                        if q == 1 and lo32:
+                            def parts(v):
+                                hi = _rne_bf16(f32(v))
+                                mid = _rne_bf16(f32(f32(v) - hi))
+                                lo = _rne_bf16(f32(f32(f32(v) - hi) - mid))
+                                return (hi, mid, lo)
+                            for pa, pb in ((1, 1), (0, 2), (2, 0), (0, 1), (1, 0), (0, 0)):
+                                for c in range(b):
+                                    acc = np.float32(acc + np.float32(parts(CI[r, c])[pa]) * np.float32(parts(CJ[s, c])[pb]))
+                        else:
+                            for c in range(b):
+                                acc = np.float32(acc + np.float32(CI[r, c]) * np.float32(CJ[s, c]))
+                        w = np.float32(Wt[r, s])
+                        Wt[r, s] = float(w - acc) if q == 1 else float(w - np.float32(float(acc) * 2.0 ** -(tI + tJ)))
+    return np.tril(W[:n, :n]), tsc
+
+
+@pytest.mark.parametrize("n", [6, 5])
+@pytest.mark.parametrize("lo16,lo32", [(3, 0), (2, 0), (3, 1)])
+@pytest.mark.parametrize("classes", [(1, 3, 2), (2, 1, 3), (3, 2, 1), (1, 1, 1)])
+def test_mp_rounding_placement_tiny(orc, n, lo16, lo32, classes):
+    """O2 against the step-by-step replica above, bit for bit, on nt = 3 tiles
+    of b = 2 (n = 5: a padded last tile) for maps putting tiles (1,0), (2,0),
+    (2,1) in the classes given: each TRSM output's FP32 rounding, storage
+    rounding with its scale, each consumer copy and the FP32/16-bit/FP8
+    update of tile (2,1) are then fixed by numpy's IEEE casts and the format
+    tables, not by the oracle's own rounding routine."""
+    M0 = synth.normal(50 + n, 36).reshape(6, 6)
+    A = (M0 @ M0.T + 6.0 * np.eye(6))[:n, :n] * 0.37
+    cmap = np.zeros((3, 3), np.uint8)
+    cmap[1, 0], cmap[2, 0], cmap[2, 1] = classes
+    Lh, info, ts = orc.mp_factor(A, 2, cmap, lo16=lo16, lo32=lo32)
+    assert info == 0
+    Lr, tr = _o2_replica(A, 2, cmap, lo16, lo32)
+    assert np.array_equal(Lh, Lr), np.max(np.abs(Lh - Lr))
+    assert np.array_equal(np.tril(ts, -1), np.tril(tr, -1))
+
+
+# ---------------------------------------------------------------- band rule
+def test_map_band_hand_case(orc):
+    """nt = 8, FP64 band 1: 28 strict-lower tiles, 5% is 1.4 tiles, so the FP32
+    band of DP/SP/HP is the single diagonal I - J = 2 (6 tiles)."""
+    d = np.subtract.outer(np.arange(8), np.arange(8))
+    low = d > 1
+    want = {1: np.where(low, 1, 0), 2: np.where(d == 2, 1, np.where(d > 2, 2, 0)), 3: np.where(low, 2, 0)}
+    for v, w in want.items():
+        assert np.array_equal(orc.map_band(8, 1, v), w.astype(np.uint8)), v
+
+
+@pytest.mark.parametrize("nt,band", [(127, 1), (64, 1), (157, 1), (20, 2), (40, 0), (3, 1), (2, 1), (1, 1)])
+def test_map_band_sp_band_holds_five_percent(orc, nt, band):
+    """DP/SP/HP: the FP32 tiles are a band next to the FP64 band, they hold at
+    least 5% of the strict-lower tiles and dropping its outermost diagonal
+    leaves less than 5% (or there is no room for more; nt = 40 with band 0 holds
+    exactly 5% in one diagonal); DP/SP and DP/HP put
+    every off-band tile in FP32 / 16-bit; the FP64 band and the diagonal stay FP64."""
+    total = nt * (nt - 1) / 2
+    d = np.subtract.outer(np.arange(nt), np.arange(nt))
+    m = orc.map_band(nt, band, 2)
+    assert np.all(m[d <= band] == 0) and np.all(m[d < 0] == 0)
+    sp = (m == 1)
+    if nt - 1 > band:
+        w32 = d[sp].max()
+        assert np.array_equal(sp, (d > band) & (d <= w32))
+        assert np.all(m[d > w32] == 2)
+        assert sp.sum() >= 0.05 * total or w32 == nt - 1
+        assert ((d > band) & (d < w32)).sum() < 0.05 * total
+    else:
+        assert not sp.any()
+    assert np.array_equal(orc.map_band(nt, band, 1), np.where(d > band, 1, 0).astype(np.uint8))
+    assert np.array_equal(orc.map_band(nt, band, 3), np.where(d > band, 2, 0).astype(np.uint8))
+
+
+def test_map_band_c4_widths(orc):
+    """nt = 127 (N = 129,600, tile 1024): 8001 strict-lower tiles; diagonals 2..5
+    hold 125 + 124 + 123 + 122 = 494 >= 400.05 tiles while 2..4 hold 372."""
+    m = orc.map_band(127, 1, 2)
+    d = np.subtract.outer(np.arange(127), np.arange(127))
+    assert np.array_equal(m == 1, (d >= 2) & (d <= 5))
+    assert (m == 1).sum() == 494
+
+
+def test_map_band_allowed_classes_raise(orc):
+    """Classes outside the allowed mask move up to the nearest allowed more precise class."""
+    d = np.subtract.outer(np.arange(10), np.arange(10))
+    assert np.array_equal(orc.map_band(10, 1, 3, allowed=0b0011), np.where(d > 1, 1, 0).astype(np.uint8))
+    assert np.array_equal(orc.map_band(10, 1, 1, allowed=0b1101), np.zeros((10, 10), np.uint8))
+    m = orc.map_band(10, 1, 2, allowed=0b0101)
+    assert set(np.unique(m[d > 1])) == {0, 2}
