@@ -186,6 +186,22 @@ int mpchol_sample(mpchol_t h, int32_t ndraws, uint64_t seed, float *Y, int64_t l
 /* As mpchol_sample with a caller-supplied device Z (n x ndraws, FP32). */
 int mpchol_sample_z(mpchol_t h, int32_t ndraws, const float *Z, int64_t ldz, float *Y, int64_t ldy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same draws as
+ * mpchol_sample -- Y (device, n x ndraws, ldy >= n, FP32) gets the values
+ * mpchol_sample(h, ndraws, seed, Y, ldy) writes, bit for bit -- without any
+ * allocation.  Z is generated into a fixed 64 MiB buffer that the library
+ * holds per device (16,777,216 FP32 values, kept until the process ends) in
+ * passes of as many whole draw columns as fit, each pass multiplied by L
+ * before the next is generated.  Only enqueues on the handle's stream (no
+ * synchronization).  Every call on one device shares that device's buffer:
+ * calls that may overlap on one GPU (other handles, streams or threads)
+ * race and must be serialized by the caller.  Errors: MPCHOL_EINVAL for null
+ * pointers, ndraws <= 0, ldy < n, or n > 16,777,216 (one draw column must
+ * fit the buffer); MPCHOL_EORDER before a successful factor; MPCHOL_EHIP if
+ * the buffer's device address could not be looked up. */
+int mpchol_sample_noalloc(mpchol_t h, int32_t ndraws, uint64_t seed, float *Y, int64_t ldy);
+
 /* The draw sequence alone: device z (count FP32 normals) and optional device
  * raw (count uint32 Philox outputs), same mapping as mpchol_sample. */
 int mpchol_normal_draws(mpchol_t h, int64_t count, uint64_t seed, float *z, uint32_t *raw);

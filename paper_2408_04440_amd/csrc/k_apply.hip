@@ -27,12 +27,15 @@ __device__ inline void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2, u
 
 // Draw e (e = i + d*n, the column-major index of an n x ndraws array) comes
 // from counter block e/4, output e%4: uniforms ((x >> 8) + 1) 2^-24 in (0,1],
-// Box-Muller on (u0,u1) and (u2,u3) in FP32.
-__global__ __launch_bounds__(256) void normal_kernel(uint64_t seed, int64_t count, int64_t n, float *Z, int64_t ldz,
-                                                     uint32_t *raw)
+// Box-Muller on (u0,u1) and (u2,u3) in FP32.  A launch writes the draws
+// e0 <= e < e0 + count (e0 a multiple of n: whole columns starting at column
+// e0/n) to Z with the column index taken relative to e0/n; each value depends
+// only on e, so a range gives the same values as the whole sequence.
+__global__ __launch_bounds__(256) void normal_kernel(uint64_t seed, int64_t e0, int64_t count, int64_t n, float *Z,
+                                                     int64_t ldz, uint32_t *raw)
 {
-    const int64_t blk = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (blk * 4 >= count) return;
+    const int64_t blk = e0 / 4 + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (blk * 4 >= e0 + count) return;
     uint32_t c0 = (uint32_t)blk, c1 = (uint32_t)((uint64_t)blk >> 32), c2 = 0, c3 = 0;
     philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
     uint32_t o[4] = {c0, c1, c2, c3};
@@ -47,24 +50,35 @@ __global__ __launch_bounds__(256) void normal_kernel(uint64_t seed, int64_t coun
     float v[4] = {r0 * k0, r0 * s0, r1 * k1, r1 * s1};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        int64_t e = blk * 4 + q;
-        if (e >= count) break;
-        if (Z) Z[(e % n) + (e / n) * ldz] = v[q];
-        if (raw) raw[e] = o[q];
+        const int64_t e = blk * 4 + q;
+        if (e < e0) continue;
+        if (e >= e0 + count) break;
+        const int64_t l = e - e0;
+        if (Z) Z[(l % n) + (l / n) * ldz] = v[q];
+        if (raw) raw[l] = o[q];
     }
+}
+
+static void launch_normal(uint64_t seed, int64_t e0, int64_t count, int64_t n, float *Z, int64_t ldz, uint32_t *raw,
+                          hipStream_t st)
+{
+    const int64_t nb = (e0 + count + 3) / 4 - e0 / 4;  // counter blocks touched
+    normal_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(seed, e0, count, n, Z, ldz, raw);
 }
 
 void launch_normal_draws(uint64_t seed, int64_t count, float *z, uint32_t *raw, hipStream_t st)
 {
-    int64_t nb = (count + 3) / 4;
-    normal_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(seed, count, count, z, count, raw);
+    launch_normal(seed, 0, count, count, z, count, raw, st);
 }
 
 void launch_normal_matrix(uint64_t seed, int64_t n, int ndraws, float *Z, int64_t ldz, hipStream_t st)
 {
-    int64_t count = n * ndraws;
-    int64_t nb = (count + 3) / 4;
-    normal_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(seed, count, n, Z, ldz, nullptr);
+    launch_normal(seed, 0, n * ndraws, n, Z, ldz, nullptr, st);
+}
+
+void launch_normal_columns(uint64_t seed, int64_t n, int64_t d0, int nd, float *Z, int64_t ldz, hipStream_t st)
+{
+    launch_normal(seed, d0 * n, n * nd, n, Z, ldz, nullptr, st);
 }
 
 // ---------------------------------------------------------------- Y = L Z

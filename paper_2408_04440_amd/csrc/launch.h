@@ -76,6 +76,8 @@ int estimate_probes();
 void launch_solve(const Tiles &T, double *B, int64_t ldb, int nrhs, hipStream_t st);
 void launch_normal_draws(uint64_t seed, int64_t count, float *z, uint32_t *raw, hipStream_t st);
 void launch_normal_matrix(uint64_t seed, int64_t n, int ndraws, float *Z, int64_t ldz, hipStream_t st);
+// draws of columns d0 .. d0+nd-1 of the n x ndraws sequence into Z's columns 0 .. nd-1
+void launch_normal_columns(uint64_t seed, int64_t n, int64_t d0, int nd, float *Z, int64_t ldz, hipStream_t st);
 void launch_lower_apply(const Tiles &T, const float *Z, int64_t ldz, float *Y, int64_t ldy, int ndraws, hipStream_t st);
 
 // ---- selector (k_mlp.hip)

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -139,6 +140,40 @@ static int hip_fail(hipError_t e, const char *expr, int line)
     return MPCHOL_EHIP;
 }
 
+// Draw buffer of mpchol_sample_noalloc: one array per device, part of the
+// library's code object (so it exists without any allocation call), held
+// until the process ends.  Host code never uses this name as an address: the
+// device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress (noalloc_scratch_setup) and kept in g_scratch.
+constexpr int64_t NOALLOC_SCRATCH_FLOATS = (int64_t)1 << 24;  // 64 MiB
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+constexpr int MAX_DEVICES = 64;
+static float *g_scratch[MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+// With `dev` current: the device address of this device's scratch array
+// (looked up on the first call for the device).  MPCHOL_EHIP on failure.
+static int noalloc_scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        snprintf(g_last_error, sizeof(g_last_error), "device %d beyond the %d devices the draw buffer covers", dev,
+                 MAX_DEVICES);
+        return MPCHOL_EHIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return MPCHOL_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        snprintf(g_last_error, sizeof(g_last_error), "hipGetSymbolAddress(scratch) failed: %s (%d) on device %d",
+                 hipGetErrorString(e), (int)e, dev);
+        (void)hipGetLastError();
+        return MPCHOL_EHIP;
+    }
+    g_scratch[dev] = (float *)p;
+    return MPCHOL_OK;
+}
+
 #define HIPCHK(x)                                                   \
     do {                                                            \
         hipError_t e_ = (x);                                        \
@@ -229,6 +264,9 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
         return MPCHOL_EHIP;
     }
     HIPCHK(hipSetDevice(opt.device));
+    // look up this device's draw buffer for mpchol_sample_noalloc; a failure
+    // is reported by that call only (it leaves g_last_error set here)
+    (void)noalloc_scratch_setup(opt.device);
 
     mpchol_handle *h = new (std::nothrow) mpchol_handle();
     if (!h) return MPCHOL_ENOMEM;
@@ -952,6 +990,40 @@ extern "C" int mpchol_sample(mpchol_t h, int32_t ndraws, uint64_t seed, float *Y
     hipError_t e = hipStreamSynchronize(h->st);
     (void)hipFree(Z);
     if (e != hipSuccess || hipGetLastError() != hipSuccess) return MPCHOL_EHIP;
+    return MPCHOL_OK;
+}
+
+extern "C" int mpchol_sample_noalloc(mpchol_t h, int32_t ndraws, uint64_t seed, float *Y, int64_t ldy)
+{
+    if (!h || !Y || ndraws <= 0 || ldy < h->n) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    if (h->n > NOALLOC_SCRATCH_FLOATS) {
+        snprintf(g_last_error, sizeof(g_last_error),
+                 "mpchol_sample_noalloc: n = %lld exceeds the draw buffer (%lld values per draw at most)",
+                 (long long)h->n, (long long)NOALLOC_SCRATCH_FLOATS);
+        return MPCHOL_EINVAL;
+    }
+    HIPCHK(hipSetDevice(h->dev));
+    float *Z = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        Z = (h->dev >= 0 && h->dev < MAX_DEVICES) ? g_scratch[h->dev] : nullptr;
+    }
+    if (!Z) {
+        snprintf(g_last_error, sizeof(g_last_error),
+                 "mpchol_sample_noalloc: the draw buffer of device %d could not be looked up", h->dev);
+        return MPCHOL_EHIP;
+    }
+    // draws per pass: as many whole columns as the buffer holds, in multiples
+    // of the 128 draws one block of the product covers when possible
+    int64_t chunk = NOALLOC_SCRATCH_FLOATS / h->n;
+    if (chunk >= 128) chunk -= chunk % 128;
+    for (int64_t d0 = 0; d0 < ndraws; d0 += chunk) {
+        const int nd = (int)std::min<int64_t>(chunk, ndraws - d0);
+        launch_normal_columns(seed, h->n, d0, nd, Z, h->n, h->st);
+        launch_lower_apply(h->tiles(), Z, h->n, Y + d0 * ldy, ldy, nd, h->st);
+    }
+    HIPCHK(hipGetLastError());
     return MPCHOL_OK;
 }
 

@@ -83,6 +83,7 @@ def lib():
             "mpchol_solve": (C.c_int, [vp, i32, vp, i64]),
             "mpchol_sample": (C.c_int, [vp, i32, u64, vp, i64]),
             "mpchol_sample_z": (C.c_int, [vp, i32, vp, i64, vp, i64]),
+            "mpchol_sample_noalloc": (C.c_int, [vp, i32, u64, vp, i64]),
             "mpchol_normal_draws": (C.c_int, [vp, i64, u64, vp, vp]),
             "mpchol_backward_error": (C.c_int, [vp, C.POINTER(d), vp]),
             "mpchol_backward_error_estimate": (C.c_int, [vp, i32, u64, C.POINTER(d)]),
@@ -246,6 +247,11 @@ def mpchol_solve(h, B, n):
 
 def mpchol_sample(h, ndraws, seed, Y, n):
     _chk(lib().mpchol_sample(h, int(ndraws), C.c_uint64(seed), _ptr(Y), _colmajor_ld(Y, n)), "mpchol_sample")
+
+
+def mpchol_sample_noalloc(h, ndraws, seed, Y, n):
+    _chk(lib().mpchol_sample_noalloc(h, int(ndraws), C.c_uint64(seed), _ptr(Y), _colmajor_ld(Y, n)),
+         "mpchol_sample_noalloc")
 
 
 def mpchol_sample_z(h, Z, Y, n):
