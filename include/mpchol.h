@@ -99,7 +99,7 @@ typedef struct mpchol_stats {
     double t_solve_ms, t_sample_ms, t_residual_ms;
     double t_gemm_ms[4];         /* profile mode: summed update-GEMM kernel time per class in the last factor */
     int64_t gemm_launches[4];    /* profile mode: number of those launches */
-    double gemm_flops[4];        /* flops of those launches */
+    double gemm_flops[4];        /* task flops of those launches: 2b^3 per GEMM and b^3 per SYRK item and step */
     int32_t fallbacks;           /* refactorizations made by verify */
     int32_t rule_used;           /* rule of the map the last factor ran with */
     double verify_first;         /* backward error (exact or estimated) of the first map verify judged;
@@ -213,6 +213,17 @@ int mpchol_normal_draws(mpchol_t h, int64_t count, uint64_t seed, float *z, uint
  * tile (strict-lower entries of a diagonal tile counted twice).  Synchronizes. */
 int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2);
 
+/* The same ratio against a caller's matrix A (Sec. III.A.3: the factor of
+ * the covariance is judged by ||A - L L^T||_F / ||A||_F):
+ * A column-major n x n, lower part read (lda >= n), in device memory if
+ * on_device, else host memory (copied to a temporary device buffer).  The
+ * stored factor is exactly widened to FP64; FP64 accumulation; ||A||_F is
+ * computed from A's lower part.  tile_res2 as in mpchol_backward_error.
+ * Temporary device memory: 2 NT^2 doubles, plus the copy of a host A.
+ * Synchronizes.  MPCHOL_EINVAL for null pointers, lda < n or A = 0. */
+int mpchol_backward_error_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_device, double *berr,
+                                 double *tile_res2);
+
 /* Randomized estimate of the same ratio: with `sets` x 64 probe vectors v
  * (N(0,1) entries from Philox with key derived from `seed`),
  * ||Sigma - L L^T||_F^2 = E ||(Sigma - L L^T) v||^2, and each product costs
@@ -271,9 +282,15 @@ int mpchol_selector_features(mpchol_t h, double eps, float *feats);
  * factor with every off-band tile at each class to measure per-tile
  * residuals, lower tiles greedily by (estimated time saved)/(added squared
  * residual) while the total stays within (eps ||S||_F)^2 / 2, then verify
- * with one factorization and raise the worst tiles until it holds.
- * labels: host NT x NT uint8 (the resulting map).  The handle must have a
- * matrix set; its tiles are reloaded and refactored several times. */
+ * with one factorization and raise the worst tiles until it holds (at most
+ * 64 rounds; after a breakdown the tiles are ranked by the residual measured
+ * for their class).  The greedy weighs a tile's time by the per-class update
+ * rates of the FP64, FP32, 16-bit and FP8 kernels at the headline size
+ * (58, 130, 600, 700 TFLOP/s).  labels: host NT x NT uint8 (the resulting
+ * map); *berr_out its measured backward error (+inf after a breakdown).
+ * MPCHOL_EBUDGET if no round met the budget (labels then hold the last map
+ * tried).  The handle must have a matrix set; its tiles are reloaded and
+ * refactored several times. */
 int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out);
 
 typedef struct mpchol_mlp *mpchol_mlp_t;

@@ -11,6 +11,7 @@ namespace mpc {
 __device__ inline double source_at(const Tiles &T, const Source &S, int I, int J, int r, int c)
 {
     int64_t i = (int64_t)I * T.b + r, j = (int64_t)J * T.b + c;
+    if (S.dense) return S.dense[i + j * S.ld];  // i >= j: the lower part
     if (S.orig) return S.orig[tile_index(I, J) * (int64_t)T.b * T.b + r + (int64_t)c * T.b];
     double v = S.sigma[i] * S.sigma[j] * exp(-fabs(S.x[i] - S.x[j]) / S.rho);
     if (i == j) v += S.nugget;

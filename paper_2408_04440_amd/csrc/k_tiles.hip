@@ -13,6 +13,7 @@ __device__ inline double source_value(const Tiles &T, const Source &S, int I, in
 {
     int64_t i = (int64_t)I * T.b + r, j = (int64_t)J * T.b + c;
     if (i >= T.n || j >= T.n) return (i == j) ? 1.0 : 0.0;
+    if (S.dense) return i >= j ? S.dense[i + j * S.ld] : S.dense[j + i * S.ld];
     if (S.orig) return S.orig[tile_index(I, J) * (int64_t)T.b * T.b + r + (int64_t)c * T.b];
     double v = S.sigma[i] * S.sigma[j] * exp(-fabs(S.x[i] - S.x[j]) / S.rho);
     if (i == j) v += S.nugget;

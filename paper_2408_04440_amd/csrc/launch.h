@@ -17,12 +17,16 @@ struct Tiles {
     int lo32;             // FP32-class updates: 0 FP32 MFMA, 1 three-way BF16 split products
 };
 
-// Source of Sigma: the generator (sigma, x, rho, nugget) or a kept FP64 copy
-// in the packed tile layout (orig != nullptr).
+// Source of Sigma: the generator (sigma, x, rho, nugget), a kept FP64 copy
+// in the packed tile layout (orig != nullptr), or a caller's column-major
+// matrix whose lower part is read (dense != nullptr, leading dimension ld;
+// norms and residuals only).
 struct Source {
     const double *sigma, *x;
     double rho, nugget;
     const double *orig;
+    const double *dense = nullptr;
+    int64_t ld = 0;
 };
 
 // Panel copies of the current step: one b*b buffer per panel row tile I.

@@ -73,6 +73,7 @@ struct mpchol_handle {
     // (npair * 12 + 1) offsets: pair p (columns 2p, 2p+1), class, part
     // (0: column 2p+1 by column 2p; 1: columns 2p+2, 2p+3 by the pair; 2: the rest by the pair)
     std::vector<int64_t> item_off;
+    std::vector<int32_t> item_syrk;  // per (pair, class, part): how many of its items are SYRK (I == J)
     uint8_t *d_qmask = nullptr;
     int32_t *d_all_items = nullptr;  // every lower tile, for the residual
     double *d_partial = nullptr, *d_tres2 = nullptr;
@@ -522,18 +523,23 @@ static void build_schedule_counts(mpchol_handle *h, std::vector<int32_t> &items,
 {
     const int nt = h->nt, npair = (nt + 1) / 2;
     h->item_off.assign((size_t)npair * 12 + 1, 0);
+    h->item_syrk.assign((size_t)npair * 12, 0);
     items.clear();
     for (int p = 0; p < npair; ++p) {
         const int c = 2 * p;
         for (int q = 0; q < 4; ++q)
             for (int part = 0; part < 3; ++part) {
-                h->item_off[((size_t)p * 4 + q) * 3 + part] = (int64_t)items.size();
+                const size_t o = ((size_t)p * 4 + q) * 3 + part;
+                h->item_off[o] = (int64_t)items.size();
                 const int jlo = part == 0 ? c + 1 : part == 1 ? c + 2 : c + 4;
                 const int jhi = part == 0 ? c + 1 : part == 1 ? c + 3 : nt - 1;
                 for (int J = jlo; J <= jhi && J < nt; ++J)
                     for (int I = J; I < nt; ++I) {
                         int cl = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
-                        if (cl == q) items.push_back((I << 16) | J);
+                        if (cl == q) {
+                            items.push_back((I << 16) | J);
+                            h->item_syrk[o] += (I == J);
+                        }
                     }
             }
     }
@@ -700,7 +706,9 @@ static int update_list(mpchol_handle *h, const Tiles &T, const Panel &P, const P
             h->gev.push_back(e0);
             h->gev.push_back(e1);
             h->gev_class.push_back(q);
-            h->gev_flops.push_back(2.0 * b3 * cnt * (P2 ? 2 : 1));
+            // task flops of the launch per step: GEMM 2b^3, SYRK b^3 (its kernel computes the lower blocks only)
+            const int syrk = h->item_syrk[o];
+            h->gev_flops.push_back(b3 * (2.0 * (cnt - syrk) + syrk) * (P2 ? 2 : 1));
         }
     }
     return MPCHOL_OK;
@@ -867,11 +875,11 @@ extern "C" int mpchol_get_tile_scales(mpchol_t h, int32_t *t)
     return MPCHOL_OK;
 }
 
-static int residual(mpchol_handle *h, double *berr, double *tile_res2)
+static int residual_of(mpchol_handle *h, const Source &S, double total_fro, double *berr, double *tile_res2)
 {
     const int nt = h->nt;
     HIPCHK(hipEventRecord(h->ev[2], h->st));
-    launch_residual_items(h->tiles(), h->source(), h->d_all_items, (int)h->ntile, h->d_partial, h->d_tres2, h->st);
+    launch_residual_items(h->tiles(), S, h->d_all_items, (int)h->ntile, h->d_partial, h->d_tres2, h->st);
     std::vector<double> r((size_t)nt * nt, 0.0);
     HIPCHK(hipMemsetAsync(h->d_scalar, 0, 8, h->st));
     HIPCHK(hipMemcpyAsync(r.data(), h->d_tres2, r.size() * 8, hipMemcpyDeviceToHost, h->st));
@@ -884,12 +892,17 @@ static int residual(mpchol_handle *h, double *berr, double *tile_res2)
     double tot = 0.0;
     for (int J = 0; J < nt; ++J)
         for (int I = J; I < nt; ++I) tot += (I == J ? 1.0 : 2.0) * r[I + (size_t)J * nt];
-    if (berr) *berr = std::sqrt(tot) / h->total_fro;
+    if (berr) *berr = std::sqrt(tot) / total_fro;
     if (tile_res2) {
         for (int J = 0; J < nt; ++J)
             for (int I = 0; I < nt; ++I) tile_res2[I + (size_t)J * nt] = (I >= J) ? r[I + (size_t)J * nt] : 0.0;
     }
     return MPCHOL_OK;
+}
+
+static int residual(mpchol_handle *h, double *berr, double *tile_res2)
+{
+    return residual_of(h, h->source(), h->total_fro, berr, tile_res2);
 }
 
 static int estimate(mpchol_handle *h, int sets, uint64_t seed, double *ratio)
@@ -936,6 +949,48 @@ extern "C" int mpchol_backward_error(mpchol_t h, double *berr, double *tile_res2
     if (h->state != S_FACTORED) return MPCHOL_EORDER;
     HIPCHK(hipSetDevice(h->dev));
     return residual(h, berr, tile_res2);
+}
+
+extern "C" int mpchol_backward_error_matrix(mpchol_t h, const double *A, int64_t lda, int32_t on_device, double *berr,
+                                            double *tile_res2)
+{
+    if (!h || !A || !berr || lda < h->n) return MPCHOL_EINVAL;
+    if (h->state != S_FACTORED) return MPCHOL_EORDER;
+    HIPCHK(hipSetDevice(h->dev));
+    const int nt = h->nt;
+    double *tmp = nullptr, *fro2 = nullptr, *amax = nullptr;
+    auto cleanup = [&]() {
+        if (tmp) (void)hipFree(tmp);
+        if (fro2) (void)hipFree(fro2);
+        if (amax) (void)hipFree(amax);
+    };
+    Source S{};
+    S.dense = A;
+    S.ld = lda;
+    int rc = dalloc(&fro2, (size_t)nt * nt * 8);
+    if (!rc) rc = dalloc(&amax, (size_t)nt * nt * 8);
+    if (!rc && !on_device) {
+        const size_t bytes = (size_t)lda * (size_t)(h->n - 1) * 8 + (size_t)h->n * 8;
+        rc = dalloc(&tmp, bytes);
+        if (!rc && hipMemcpyAsync(tmp, A, bytes, hipMemcpyHostToDevice, h->st) != hipSuccess) rc = MPCHOL_EHIP;
+        S.dense = tmp;
+    }
+    if (!rc && hipMemsetAsync(fro2, 0, (size_t)nt * nt * 8, h->st) != hipSuccess) rc = MPCHOL_EHIP;
+    std::vector<double> f2((size_t)nt * nt, 0.0);
+    if (!rc) {
+        launch_norms(h->tiles(), S, fro2, amax, h->st);
+        if (hipMemcpyAsync(f2.data(), fro2, f2.size() * 8, hipMemcpyDeviceToHost, h->st) != hipSuccess ||
+            hipStreamSynchronize(h->st) != hipSuccess || hipGetLastError() != hipSuccess)
+            rc = MPCHOL_EHIP;
+    }
+    if (!rc) {
+        double tot = 0.0;
+        for (int J = 0; J < nt; ++J)
+            for (int I = J; I < nt; ++I) tot += (I == J ? 1.0 : 2.0) * f2[I + (size_t)J * nt];
+        rc = (tot > 0.0) ? residual_of(h, S, std::sqrt(tot), berr, tile_res2) : MPCHOL_EINVAL;
+    }
+    cleanup();
+    return rc;
 }
 
 extern "C" int mpchol_set_verify(mpchol_t h, int32_t mode, double eps)
@@ -1140,24 +1195,33 @@ extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, d
     }
     // verify; raise the worst tiles until the measured error fits
     double be = INFINITY;
+    bool fits = false;
     for (int it = 0; it < 64; ++it) {
         rc = apply_map(h, MPCHOL_RULE_USER, eps, cur.data());
         if (rc) return rc;
         int64_t inf = 0;
         rc = run_factor(h, &inf);
         if (rc < 0) return rc;
+        const bool broke = (rc == MPCHOL_NOT_SPD);
         std::vector<double> tr((size_t)nt * nt, 0.0);
-        if (rc == MPCHOL_OK) {
+        if (!broke) {
             rc = residual(h, &be, tr.data());
             if (rc) return rc;
-            if (be <= eps) break;
+            if (be <= eps) {
+                fits = true;
+                break;
+            }
+        } else {
+            be = INFINITY;
         }
-        // raise the 5% of lowered tiles with the largest residual by one level
+        // raise the 5% of lowered tiles with the largest residual by one level;
+        // after a breakdown there is no residual of this map, so the tiles are
+        // ranked by the residual measured for their class in the first phase
         std::vector<std::pair<double, size_t>> v;
         for (int J = 0; J < nt; ++J)
             for (int I = J + 1; I < nt; ++I) {
                 size_t t = I + (size_t)J * nt;
-                if (cur[t] > P64) v.push_back({tr[t], t});
+                if (cur[t] > P64) v.push_back({broke ? res[cur[t]][t] : tr[t], t});
             }
         if (v.empty()) break;
         std::sort(v.begin(), v.end(), [](auto &a, auto &b2) { return a.first > b2.first; });
@@ -1171,5 +1235,12 @@ extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, d
     }
     std::memcpy(labels, cur.data(), cur.size());
     if (berr_out) *berr_out = be;
+    if (!fits) {
+        // the map left in labels is the last one tried; it missed the budget or broke down
+        snprintf(g_last_error, sizeof(g_last_error),
+                 "mpchol_selector_labels: the raised map still misses the budget (backward error %.3e, eps %.3e)",
+                 be, eps);
+        return MPCHOL_EBUDGET;
+    }
     return MPCHOL_OK;
 }

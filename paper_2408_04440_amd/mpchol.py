@@ -87,6 +87,7 @@ def lib():
             "mpchol_normal_draws": (C.c_int, [vp, i64, u64, vp, vp]),
             "mpchol_backward_error": (C.c_int, [vp, C.POINTER(d), vp]),
             "mpchol_backward_error_estimate": (C.c_int, [vp, i32, u64, C.POINTER(d)]),
+            "mpchol_backward_error_matrix": (C.c_int, [vp, vp, i64, i32, C.POINTER(d), vp]),
             "mpchol_get_factor": (C.c_int, [vp, vp, i64]),
             "mpchol_get_tile_scales": (C.c_int, [vp, vp]),
             "mpchol_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
@@ -147,6 +148,24 @@ def _colmajor_ld(t, n):
     return s[1] if t.shape[1] > 1 else max(n, t.shape[0])
 
 
+def _check_device(t, dtype, name, rows=None, cols=None, numel=None):
+    """A device buffer the kernels will read or write: a CUDA torch tensor of
+    `dtype` holding at least `rows` x `cols` (a column-major view) or `numel`
+    elements.  Raises ValueError before any library call, so a wrong buffer
+    never reaches a kernel."""
+    if not hasattr(t, "is_cuda") or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA torch tensor")
+    if str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, need {numel}")
+    if rows is not None:
+        r = t.shape[0]
+        c = 1 if t.dim() == 1 else t.shape[1]
+        if t.dim() > 2 or r < rows or (cols is not None and c < cols):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, need at least ({rows}, {cols if cols else 1})")
+
+
 def _stream_ptr(stream):
     if stream is None:
         try:
@@ -189,13 +208,19 @@ def mpchol_set_matrix(h, A, n=None):
         A = np.asfortranarray(A, dtype=np.float64)
         rc = lib().mpchol_set_matrix(h, A.ctypes.data_as(C.c_void_p), A.shape[0], 0)
     else:
+        _check_device(A, "float64", "A", rows=A.shape[0], cols=A.shape[0])
         rc = lib().mpchol_set_matrix(h, _ptr(A), _colmajor_ld(A, A.shape[0]), 1)
     _chk(rc, "mpchol_set_matrix")
 
 
-def mpchol_set_generator(h, sigma, x, rho, nugget):
-    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-    x = np.ascontiguousarray(x, dtype=np.float64)
+def mpchol_set_generator(h, sigma, x, rho, nugget, n=None):
+    """sigma, x: host arrays of at least n values (n: the handle's order, read
+    from its stats when not given)."""
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64).ravel()
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    n = mpchol_get_stats(h)["n"] if n is None else n
+    if sigma.size < n or x.size < n:
+        raise ValueError(f"mpchol_set_generator: sigma ({sigma.size}) and x ({x.size}) need {n} values")
     _chk(lib().mpchol_set_generator(h, sigma.ctypes.data_as(C.c_void_p), x.ctypes.data_as(C.c_void_p), float(rho),
                                     float(nugget)), "mpchol_set_generator")
 
@@ -208,8 +233,9 @@ def mpchol_set_samples(h, Xi, scale, nugget, m=None):
         rc = lib().mpchol_set_samples(h, Xi.ctypes.data_as(C.c_void_p), Xi.shape[0], Xi.shape[1], float(scale),
                                       float(nugget), 0)
     else:
-        rc = lib().mpchol_set_samples(h, _ptr(Xi), _colmajor_ld(Xi, Xi.shape[0]), int(Xi.shape[1] if m is None else m),
-                                      float(scale), float(nugget), 1)
+        m = int(Xi.shape[1] if m is None else m)
+        _check_device(Xi, "float64", "Xi", rows=Xi.shape[0], cols=m)
+        rc = lib().mpchol_set_samples(h, _ptr(Xi), _colmajor_ld(Xi, Xi.shape[0]), m, float(scale), float(nugget), 1)
     _chk(rc, "mpchol_set_samples")
 
 
@@ -242,25 +268,36 @@ def mpchol_logdet(h):
 def mpchol_solve(h, B, n):
     """B: torch float64 column-major (n x nrhs) view or 1-D (n,) tensor on the device; overwritten."""
     nrhs = 1 if B.dim() == 1 else B.shape[1]
+    _check_device(B, "float64", "B", rows=n, cols=nrhs)
     _chk(lib().mpchol_solve(h, int(nrhs), _ptr(B), _colmajor_ld(B, n)), "mpchol_solve")
 
 
 def mpchol_sample(h, ndraws, seed, Y, n):
+    _check_device(Y, "float32", "Y", rows=n, cols=int(ndraws))
     _chk(lib().mpchol_sample(h, int(ndraws), C.c_uint64(seed), _ptr(Y), _colmajor_ld(Y, n)), "mpchol_sample")
 
 
 def mpchol_sample_noalloc(h, ndraws, seed, Y, n):
+    _check_device(Y, "float32", "Y", rows=n, cols=int(ndraws))
     _chk(lib().mpchol_sample_noalloc(h, int(ndraws), C.c_uint64(seed), _ptr(Y), _colmajor_ld(Y, n)),
          "mpchol_sample_noalloc")
 
 
 def mpchol_sample_z(h, Z, Y, n):
     nd = 1 if Z.dim() == 1 else Z.shape[1]
+    _check_device(Z, "float32", "Z", rows=n, cols=nd)
+    _check_device(Y, "float32", "Y", rows=n, cols=nd)
     _chk(lib().mpchol_sample_z(h, int(nd), _ptr(Z), _colmajor_ld(Z, n), _ptr(Y), _colmajor_ld(Y, n)),
          "mpchol_sample_z")
 
 
 def mpchol_normal_draws(h, count, seed, z=None, raw=None):
+    if z is not None:
+        _check_device(z, "float32", "z", numel=int(count))
+    if raw is not None:
+        if str(raw.dtype) not in ("torch.int32", "torch.uint32"):
+            raise ValueError(f"raw: expected a 32-bit integer tensor, got {raw.dtype}")
+        _check_device(raw, str(raw.dtype)[6:], "raw", numel=int(count))
     _chk(lib().mpchol_normal_draws(h, int(count), C.c_uint64(seed), _ptr(z), _ptr(raw)), "mpchol_normal_draws")
 
 
@@ -275,6 +312,26 @@ def mpchol_backward_error(h, tiles=False, nt=None):
     return (be.value, tr) if tiles else be.value
 
 
+def mpchol_backward_error_matrix(h, A, tiles=False, nt=None):
+    """||A - L L^T||_F / ||A||_F for the caller's A: a numpy array (host) or a
+    torch float64 column-major device view; with tiles=True also the per-tile
+    squared residuals (nt x nt)."""
+    be = C.c_double(0.0)
+    tr = None
+    if tiles:
+        nt = nt if nt is not None else mpchol_get_stats(h)["nt"]
+        tr = np.zeros((nt, nt), order="F")
+    trp = None if tr is None else tr.ctypes.data_as(C.c_void_p)
+    if isinstance(A, np.ndarray):
+        A = np.asfortranarray(A, dtype=np.float64)
+        rc = lib().mpchol_backward_error_matrix(h, A.ctypes.data_as(C.c_void_p), A.shape[0], 0, C.byref(be), trp)
+    else:
+        _check_device(A, "float64", "A")
+        rc = lib().mpchol_backward_error_matrix(h, _ptr(A), _colmajor_ld(A, A.shape[0]), 1, C.byref(be), trp)
+    _chk(rc, "mpchol_backward_error_matrix")
+    return (be.value, tr) if tiles else be.value
+
+
 def mpchol_backward_error_estimate(h, sets=2, seed=7):
     be = C.c_double(0.0)
     _chk(lib().mpchol_backward_error_estimate(h, int(sets), C.c_uint64(seed), C.byref(be)),
@@ -283,6 +340,7 @@ def mpchol_backward_error_estimate(h, sets=2, seed=7):
 
 
 def mpchol_get_factor(h, L, n):
+    _check_device(L, "float64", "L", rows=n, cols=n)
     _chk(lib().mpchol_get_factor(h, _ptr(L), _colmajor_ld(L, n)), "mpchol_get_factor")
 
 

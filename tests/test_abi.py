@@ -6,6 +6,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -119,3 +121,56 @@ def test_sht_binding_checks_shapes():
     with pytest.raises(ValueError):
         M.mpchol_sht_inverse(C.c_void_p(1), torch.zeros((2, 64), dtype=torch.float64),
                              torch.zeros((3, 9, 15), dtype=torch.float64), 8)
+
+
+class _FakeDev:
+    """Stands in for a CUDA tensor (no GPU here): only what the binding's
+    checks read."""
+
+    def __init__(self, shape, dtype, cuda=True):
+        self.shape, self.is_cuda = tuple(shape), cuda
+        self.dtype = dtype
+
+    def dim(self):
+        return len(self.shape)
+
+    def numel(self):
+        n = 1
+        for s in self.shape:
+            n *= s
+        return n
+
+    def stride(self):
+        return (1, self.shape[0]) if len(self.shape) == 2 else (1,)
+
+    def data_ptr(self):
+        raise AssertionError("the library must not be reached")
+
+
+def test_binding_rejects_wrong_device_buffers():
+    """Wrong dtype, host memory or too few rows/columns are refused by the
+    binding before any library call, so a short buffer never reaches a kernel."""
+    import torch
+
+    import paper_2408_04440_amd.mpchol as M
+
+    n = 1024
+    good32 = _FakeDev((n, 8), torch.float32)
+    cases = [
+        lambda: M.mpchol_sample(None, 8, 1, _FakeDev((n, 8), torch.float64), n),      # wrong dtype
+        lambda: M.mpchol_sample(None, 9, 1, good32, n),                                # too few columns
+        lambda: M.mpchol_sample(None, 8, 1, _FakeDev((n - 1, 8), torch.float32), n),  # too few rows
+        lambda: M.mpchol_sample(None, 8, 1, torch.zeros((8, n), dtype=torch.float32).T, n),  # host tensor
+        lambda: M.mpchol_sample_noalloc(None, 8, 1, _FakeDev((n, 4), torch.float32), n),
+        lambda: M.mpchol_sample_z(None, good32, _FakeDev((n, 7), torch.float32), n),
+        lambda: M.mpchol_sample_z(None, _FakeDev((n, 8), torch.float16), good32, n),
+        lambda: M.mpchol_solve(None, _FakeDev((n, 2), torch.float32), n),             # solve needs float64
+        lambda: M.mpchol_solve(None, _FakeDev((n - 5,), torch.float64), n),
+        lambda: M.mpchol_get_factor(None, _FakeDev((n, n - 1), torch.float64), n),
+        lambda: M.mpchol_normal_draws(None, 100, 1, _FakeDev((99,), torch.float32)),
+        lambda: M.mpchol_normal_draws(None, 100, 1, None, _FakeDev((100,), torch.float32)),
+        lambda: M.mpchol_set_generator(None, np.ones(n - 1), np.ones(n), 5.0, 1e-8, n=n),
+    ]
+    for i, f in enumerate(cases):
+        with pytest.raises(ValueError):
+            f()
