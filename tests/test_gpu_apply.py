@@ -97,14 +97,17 @@ def test_sample_z_matches_oracle_product(orc, rule, eps):
         be = mod.mpchol_backward_error(h)
     finally:
         mod.mpchol_destroy(h)
+    # the oracle's FP64 product of the GPU's own factor (its represented
+    # values) with the same draws: only the FP32 products and accumulation
+    # of the draws kernel differ (about 1e-7)
+    Yg = orc.lower_matmul(Lg, Z.astype(np.float64))
+    rel = np.linalg.norm(Y - Yg) / np.linalg.norm(Yg)
+    # for information: the distance to the product with the exact factor
     A = orc.cov_dense(sigma, x, 5.0, 1e-8)
     Lo, _ = orc.potrf(A)
     Yo = orc.lower_matmul(Lo, Z.astype(np.float64))
-    rel = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
-    # FP32 products and accumulation (~1e-7) plus the factor's own distance to the exact one
-    fac = np.linalg.norm(Lg - Lo) / np.linalg.norm(Lo)
-    log(f"  sample_z rule={rule}: rel={rel:.2e} factor dist={fac:.2e}")
-    assert rel <= 1e-5 + 4 * fac
+    log(f"  sample_z rule={rule}: rel to L_gpu Z {rel:.2e}; to L_exact Z {np.linalg.norm(Y - Yo) / np.linalg.norm(Yo):.2e}")
+    assert rel <= 1e-5
 
 
 def test_sample_is_philox_then_product(orc):

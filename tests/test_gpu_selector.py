@@ -140,7 +140,6 @@ def test_features_and_learned_map(orc, L, tile):
         Fg = mod.mpchol_selector_features(h, eps, nt).astype(np.float64)
         mod.mpchol_selector_set(h, P)
         mg = mod.mpchol_precision_map(h, mod.RULE_LEARNED, eps)
-        assert mod.mpchol_factor(h) == 0 or True
     finally:
         mod.mpchol_destroy(h)
     assert np.max(np.abs(Fg - Fr)) <= 1e-5 * max(1.0, np.max(np.abs(Fr)))

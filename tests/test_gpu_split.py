@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from _gpu import M, factor_dense, log
+from _gpu import M, factor_dense, log, same_factor_residuals, tile_rel, tile_residual_levels
 
 pytestmark = pytest.mark.gpu
 
@@ -60,9 +60,10 @@ def test_split_user_map_against_replay(orc, n, tile, seed, lo16):
         assert mod.mpchol_factor(h) == 0
         Lg = factor_dense(h, n)
         tg = mod.mpchol_get_tile_scales(h, nt)
-        be_g = mod.mpchol_backward_error(h)
+        be_g, tr_g = mod.mpchol_backward_error(h, tiles=True)
     finally:
         mod.mpchol_destroy(h)
+    same_factor_residuals(be_g, tr_g, orc.backward_error(A, Lg), orc.tile_residual2(A, Lg, tile), A, tile)
     L0, _, t0 = orc.mp_factor(A, tile, um, lo16=olo, order=0, lo32=1)
     L1, _, _ = orc.mp_factor(A, tile, um, lo16=olo, order=1, lo32=1)
     assert np.array_equal(tg, t0)
@@ -71,7 +72,9 @@ def test_split_user_map_against_replay(orc, n, tile, seed, lo16):
     be_o = orc.backward_error(A, L0)
     log(f"  split user map n={n}: be_gpu={be_g:.3e} be_O2={be_o:.3e} |G-O2|={d_go:.2e} |O2-O2'|={d_oo:.2e}")
     assert d_go <= 8.0 * d_oo + 1e-14
+    assert tile_rel(Lg, L0, tile) <= 8.0 * max(tile_rel(L1, L0, tile), 1e-14) + 1e-13
     assert abs(be_g - be_o) <= 0.25 * be_o
+    tile_residual_levels(tr_g, orc.tile_residual2(A, L0, tile), A, tile)
 
 
 @pytest.mark.parametrize("rho,eps", [(2.0, 1e-9), (5.0, 1e-9)])
