@@ -120,9 +120,28 @@ def cpu_baseline(sigma, x, rho, nugget, target_s=15.0):
             break
         ns *= 2
     ld_ref = oracle.markov_logdet(sigma, x, rho, nugget)
-    return {"value": ns ** 3 / 3.0 / t / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+    n = len(sigma)
+    rate = ns ** 3 / 3.0 / t
+    return {"value": rate / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"plain FP64 right-looking Cholesky of the leading {ns}x{ns} block of the same covariance "
-                      f"({t:.2f} s, info={info})"}, ld_ref
+                      f"({t:.2f} s, info={info})",
+            # the full workload at the sample's N^3 rate (not run: the oracle's dense FP64 matrix
+            # alone would take 8 N^2 bytes of host memory)
+            "extrapolated_full_s": round(n ** 3 / 3.0 / rate, 1),
+            "extrapolated_full_note": f"N={n} at the measured rate of the {ns}x{ns} sample; extrapolated, not run"}, ld_ref
+
+
+def cpu_model():
+    """Model name of the host CPU (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_sht(M, torch, L, T, reps, cpu):
@@ -187,13 +206,50 @@ def bench_sht(M, torch, L, T, reps, cpu):
     return out
 
 
+def bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, lo32):
+    """The band precision variants of Sec. IV.B on the same workload, one
+    untimed run then one timed run each: DP/SP (one FP64 band, the rest
+    FP32), DP/SP/HP (then the narrowest band holding >= 5% of the
+    strict-lower tiles in FP32, the rest 16-bit), DP/HP (the rest 16-bit).
+    Backward error by the randomized estimate (64 probes; relative standard
+    deviation about 0.09); these maps ignore the accuracy budget."""
+    names = {1: "DP/SP", 2: "DP/SP/HP", 3: "DP/HP"}
+    out = {}
+    for v in (1, 2, 3):
+        hb = M.mpchol_create(n, tile, stream=torch.cuda.current_stream(), lo16=cfg["lo16"], allowed=cfg["allowed"],
+                             band_variant=v, lo32=lo32)
+        try:
+            ts = []
+            for r in range(2):
+                M.mpchol_set_generator(hb, sigma, x, rho, nugget)
+                cm = M.mpchol_precision_map(hb, M.RULE_BAND)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = M.mpchol_factor(hb)
+                ts.append((time.perf_counter() - t0) * 1e3)
+            st = M.mpchol_get_stats(hb)
+            be = M.mpchol_backward_error_estimate(hb, 1, 5) if info == 0 else None
+        finally:
+            M.mpchol_destroy(hb)
+        nt = st["nt"]
+        out[names[v]] = {"t_factor_ms": round(ts[-1], 1), "tflops": round(flops / ts[-1] / 1e9, 3),
+                         "speedup_vs_fp64": None if fp64 is None else round(flops / ts[-1] / 1e9 / fp64, 3),
+                         "backward_error_estimate": be, "info": info,
+                         "tiles_per_class": np.bincount(cm[np.tril_indices(nt, -1)], minlength=4).tolist()}
+        log(f"  band {names[v]}: {out[names[v]]}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c4", choices=sorted(CONFIGS))
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="timed runs of the plain FP64 path (median reported; one untimed warm-up run first)")
+    ap.add_argument("--no-band", action="store_true",
+                    help="skip the band variants (DP/SP, DP/SP/HP, DP/HP) timed after the steps")
     ap.add_argument("--no-berr", action="store_true", help="skip the FP64 residual check")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rho", type=float, default=None, help="override the workload's rho")
@@ -345,23 +401,25 @@ def main():
                 "traffic": measured_traffic(f"update_{CLASS[q]}") if args.config == "c4" else None,
                 "algorithmic_flops_per_launch": st["gemm_flops"][q] / max(st["gemm_launches"][q], 1),
                 "launches": st["gemm_launches"][q],
-                "mixed_roofline_frac": round(t_roof / (t_med / 1e3), 4),
-                "fp64_peak_frac": round(value / PEAK[0], 4)}
+                "mixed_roofline_frac": round(t_roof / (t_med / 1e3), 4)}
 
     # plain FP64 path, same library
-    fp64 = None
+    fp64, t64 = None, []
     if rule != M.RULE_FP64 and args.fp64_steps > 0:
-        t64 = []
-        for _ in range(args.fp64_steps):
+        for r in range(args.fp64_steps + 1):  # the first run is an untimed warm-up
             M.mpchol_set_generator(h, sigma, x, rho, nugget)
             M.mpchol_precision_map(h, M.RULE_FP64)
             torch.cuda.synchronize()
             t640 = time.perf_counter()
             if M.mpchol_factor(h):
                 raise RuntimeError("FP64 factorization failed")
-            t64.append((time.perf_counter() - t640) * 1e3)
-            log(f"  fp64: t_factor={t64[-1]:.1f} ms  {flops / t64[-1] / 1e9:.2f} TFLOP/s")
+            tr = (time.perf_counter() - t640) * 1e3
+            log(f"  fp64 {'warmup' if r == 0 else 'run ' + str(r)}: t_factor={tr:.1f} ms  {flops / tr / 1e9:.2f} TFLOP/s")
+            if r > 0:
+                t64.append(tr)
         fp64 = flops / statistics.median(t64) / 1e9
+        # the plain FP64 path as a fraction of the FP64 MFMA peak
+        roofline["fp64_path_frac"] = round(fp64 / PEAK[0], 4)
     compare = {}
     for name in [c for c in args.compare.split(",") if c]:
         M.mpchol_set_verify(h, 0 if name == "learned_unverified" else 2, eps)
@@ -399,6 +457,9 @@ def main():
         log(f"  producer: {producer}")
         del Xs
     M.mpchol_destroy(h)
+    band = None
+    if not args.no_band and args.config in ("c3", "c4"):
+        band = bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, extra["lo32"])
     sht = None
     if args.sht > 0:
         sht = bench_sht(M, torch, args.sht, sht_T, max(args.steps, 1), False)
@@ -429,6 +490,8 @@ def main():
         "fallbacks": st["fallbacks"],
         "verify_first": verify_value(st["verify_first"]),
         "compare": compare or None,
+        "fp64_ms": None if not t64 else [round(v, 1) for v in t64],
+        "band_variants": band,
         "producer": producer,
         "sht": sht,
         "backward_error": berr,
