@@ -85,7 +85,11 @@ def lib():
         L.orc_map_norm.argtypes = [i64, dp, d, d, i32, C.c_uint, i32, C.POINTER(C.c_uint8)]
         L.orc_map_band.argtypes = [i64, i32, i32, C.c_uint, C.POINTER(C.c_uint8)]
         L.orc_mp_factor.restype = i64
-        L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32, i32]
+        L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32, i32,
+                                    i32, i32]
+        L.orc_ozaki_gemm.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
+        L.orc_ozaki_row_exp.restype = i32
+        L.orc_ozaki_row_exp.argtypes = [dp, i64, i64]
         L.orc_split3.restype = C.c_float
         L.orc_split3.argtypes = [d, i32]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
@@ -264,12 +268,14 @@ def map_band(nt, band=1, variant=3, allowed=0xF):
     return out
 
 
-def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0):
+def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0, lo64=0, band=1):
     """O2: (Lhat, info, tscale) -- the tile algorithm replayed with explicit rounding.
 
     cmap is an nt x nt class map (lower part used; 0 FP64, 1 FP32, 2 16-bit, 3 FP8);
     order 0/1 sums the update products in increasing/decreasing order;
-    lo32 = 1 forms FP32-class products from three-way BF16 splits.
+    lo32 = 1 forms FP32-class products from three-way BF16 splits;
+    lo64 = 1 forms the FP64-class products of tiles farther than `band` from
+    the diagonal as exact integer products of row-scaled panels (ozaki_gemm).
     """
     A = _fortran(A)
     n = A.shape[0]
@@ -279,8 +285,28 @@ def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0):
     Lh = np.zeros((n, n), order="F")
     ts = np.zeros((nt, nt), dtype=np.int32, order="F")
     info = lib().orc_mp_factor(n, b, _dp(A), n, cmap.ctypes.data_as(C.POINTER(C.c_uint8)), lo16, _dp(Lh), n,
-                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order), int(lo32))
+                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order), int(lo32), int(lo64), int(band))
     return Lh, int(info), ts
+
+
+def ozaki_gemm(A, B):
+    """D = A B^T with FP64-class products emulated by exact integer products:
+    each row scaled by 2^e (row max in [2^52, 2^53)), rounded to integers,
+    the integer products summed exactly, the sum rounded once to FP64 and
+    scaled back."""
+    A, B = _fortran(A), _fortran(B)
+    m, k = A.shape
+    n = B.shape[0]
+    assert B.shape[1] == k
+    D = np.empty((m, n), order="F")
+    lib().orc_ozaki_gemm(m, n, k, _dp(A), m, _dp(B), n, _dp(D), m)
+    return D
+
+
+def ozaki_row_exp(row):
+    """Scale exponent e of a row: max |row| 2^e in [2^52, 2^53) (0 for a zero row)."""
+    r = _f64(row)
+    return int(lib().orc_ozaki_row_exp(_dp(r), 1, r.size))
 
 
 def split3(v):

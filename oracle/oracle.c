@@ -487,6 +487,79 @@ void orc_map_band(int64_t nt, int band, int variant, unsigned allowed, uint8_t *
 }
 
 /* ------------------------------------------------------------------------
+ * FP64-class products emulated with exact integer products (the Ozaki
+ * scheme II of Ozaki, Uchino and Imamura: scale each row to integers, form
+ * the integer product exactly, scale back).  Definition, for D = A B^T with
+ * A (m x k) and B (n x k):
+ *   - row r of an operand X: mu_r = max_c |X_rc|; e_r = 0 if mu_r = 0, else
+ *     e_r = 53 - E_r with mu_r = f 2^E_r, f in [1/2, 1), so that
+ *     mu_r 2^e_r lies in [2^52, 2^53);
+ *   - integers x_rc = rint(X_rc 2^e_r) (round to nearest even; |x| <= 2^53);
+ *   - P_rs = sum_c a_rc b_sc, exact (here in 128-bit integers: each term is
+ *     below 2^106 in magnitude, the sum below 2^116 for k <= 1024);
+ *   - D_rs = round_f64(P_rs) 2^-(e_r + f_s), one rounding to nearest even.
+ * The integer product does not depend on a summation order; how it is
+ * formed (by residues on the GPU) is not part of the definition.
+ * Pinned by: brute force with Python integers and its correctly rounded
+ * int-to-float conversion (bit for bit, including conversion halfway
+ * cases), exactness on integer inputs, and the error bound
+ * |D_rs - (A B^T)_rs| <= 2k 2^-53 mu_r nu_s (1 + 2^-52) + |(A B^T)_rs| 2^-53
+ * (each scaled entry moves by at most half a unit, 2^-53 of its row max).
+ * ---------------------------------------------------------------------- */
+static int ozaki_row_exp(double mu)
+{
+    if (!(mu > 0.0)) return 0;
+    int E;
+    frexp(mu, &E);
+    return 53 - E;
+}
+
+/* Row exponent of row r of the column-major block X (len entries, stride ld). */
+int orc_ozaki_row_exp(const double *X, int64_t ld, int64_t len)
+{
+    double mu = 0.0;
+    for (int64_t c = 0; c < len; ++c)
+        if (fabs(X[c * ld]) > mu) mu = fabs(X[c * ld]);
+    return ozaki_row_exp(mu);
+}
+
+/* The integer of entry x scaled by 2^e (round to nearest even). */
+static int64_t ozaki_int(double x, int e) { return (int64_t)nearbyint(ldexp(x, e)); }
+
+static double ozaki_value(__int128 P, int e)
+{
+    return ldexp((double)P, -e);  /* the 128-bit to double conversion rounds to nearest even */
+}
+
+/* D (m x n, ldd) = A B^T by the definition above; A (m x k, lda), B (n x k, ldb),
+ * all column-major. */
+void orc_ozaki_gemm(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B, int64_t ldb,
+                    double *D, int64_t ldd)
+{
+    int64_t *a = malloc(sizeof(int64_t) * (size_t)(m * k + 1)), *bq = malloc(sizeof(int64_t) * (size_t)(n * k + 1));
+    int *ea = malloc(sizeof(int) * (size_t)(m + 1)), *eb = malloc(sizeof(int) * (size_t)(n + 1));
+    for (int64_t r = 0; r < m; ++r) {
+        ea[r] = orc_ozaki_row_exp(A + r, lda, k);
+        for (int64_t c = 0; c < k; ++c) a[r * k + c] = ozaki_int(A[r + c * lda], ea[r]);
+    }
+    for (int64_t s = 0; s < n; ++s) {
+        eb[s] = orc_ozaki_row_exp(B + s, ldb, k);
+        for (int64_t c = 0; c < k; ++c) bq[s * k + c] = ozaki_int(B[s + c * ldb], eb[s]);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < n; ++s)
+        for (int64_t r = 0; r < m; ++r) {
+            __int128 P = 0;
+            for (int64_t c = 0; c < k; ++c) P += (__int128)a[r * k + c] * bq[s * k + c];
+            D[r + s * ldd] = ozaki_value(P, ea[r] + eb[s]);
+        }
+    free(a);
+    free(bq);
+    free(ea);
+    free(eb);
+}
+
+/* ------------------------------------------------------------------------
  * O2: the mixed-precision tile Cholesky replayed on the CPU with explicit
  * rounding (Sec. III.D with the task graph and sender-side conversion of
  * Sec. V.A).  The matrix is padded to NT*b with an identity block.
@@ -501,6 +574,10 @@ void orc_map_band(int64_t nt, int band, int variant, unsigned allowed, uint8_t *
  *       class: FP64 = stored value; FP32 = round_f32(stored);
  *       16-bit/FP8 = round_q(round_f32(stored * 2^t_q)) with its own scale t_q;
  *     SYRK(I,I) and FP64-class GEMM(I,J): W -= C64_I C64_J^T in FP64;
+ *       with lo64 = 1, an FP64-class GEMM of a tile with |I-J| > band64 is
+ *       W -= D(C64_I, C64_J), the exact-integer-product emulation defined
+ *       above (row scales of each panel tile taken once, at its conversion);
+ *       SYRK and the tiles within band64 of the diagonal keep FP64 sums;
  *     FP32-class GEMM: acc = sum of float products (float adds, k order),
  *       W = round_f32(W - acc);
  *       with lo32 = 1 the FP32 operands are split into three BF16 parts,
@@ -536,7 +613,7 @@ float orc_split3(double v, int part)
 }
 
 int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const uint8_t *map, int lo16,
-                      double *Lhat, int64_t ldl, int32_t *tscale, int order, int lo32)
+                      double *Lhat, int64_t ldl, int32_t *tscale, int order, int lo32, int lo64, int band64)
 {
     int64_t nt = (n + b - 1) / b, np = nt * b;
     double *W = malloc(sizeof(double) * (size_t)np * np);
@@ -549,6 +626,9 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
     if (lo32)
         for (int p = 0; p < 3; ++p) S3[p] = malloc(sizeof(float) * (size_t)np * b);
     int *tq = malloc(sizeof(int) * nt * 4);
+    /* with lo64: the integers and row exponents of each FP64 panel copy */
+    int64_t *Z64 = lo64 ? malloc(sizeof(int64_t) * (size_t)np * b) : NULL;
+    int *ez = lo64 ? malloc(sizeof(int) * (size_t)np) : NULL;
     int64_t info = 0;
 
     for (int64_t t = 0; t < nt * nt; ++t) tscale[t] = 0;
@@ -632,6 +712,12 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                             for (int p = 0; p < 3; ++p) S3[p][(i0 + r) + (size_t)c * np] = orc_split3(cv, p);
                     }
             }
+            if (lo64)
+                for (int64_t r = 0; r < b; ++r) {
+                    const double *row = C[ORC_P64] + i0 + r;
+                    ez[i0 + r] = orc_ozaki_row_exp(row, np, b);
+                    for (int64_t c = 0; c < b; ++c) Z64[(i0 + r) * b + c] = ozaki_int(row[(size_t)c * np], ez[i0 + r]);
+                }
         }
 
         /* SYRK / GEMM updates of the trailing tiles */
@@ -645,7 +731,16 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                 float acc32[b > 0 ? b : 1];
                 for (int64_t s = 0; s < b; ++s) {
                     /* acc_r = sum_c C_I[r,c] C_J[s,c], terms in c order */
-                    if (cls == ORC_P64) {
+                    if (cls == ORC_P64 && lo64 && I - J > band64) {
+                        /* exact integer products of the scaled panel rows, one rounding each */
+                        const int64_t *bz = Z64 + (j0 + s) * b;
+                        for (int64_t r = 0; r < b; ++r) {
+                            const int64_t *az = Z64 + (i0 + r) * b;
+                            __int128 P = 0;
+                            for (int64_t c = 0; c < b; ++c) P += (__int128)az[c] * bz[c];
+                            W[IDX(i0 + r, j0 + s)] -= ozaki_value(P, ez[i0 + r] + ez[j0 + s]);
+                        }
+                    } else if (cls == ORC_P64) {
                         for (int64_t r = 0; r < b; ++r) acc64[r] = 0.0;
                         for (int64_t cc = 0; cc < b; ++cc) {
                             int64_t c = order ? b - 1 - cc : cc;
@@ -693,6 +788,8 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
     for (int c = 0; c < 4; ++c) free(C[c]);
     for (int p = 0; p < 3; ++p) free(S3[p]);
     free(tq);
+    free(Z64);
+    free(ez);
     free(W);
     return info;
 }

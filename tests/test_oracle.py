@@ -782,3 +782,109 @@ def test_map_band_allowed_classes_raise(orc):
     assert np.array_equal(orc.map_band(10, 1, 1, allowed=0b1101), np.zeros((10, 10), np.uint8))
     m = orc.map_band(10, 1, 2, allowed=0b0101)
     assert set(np.unique(m[d > 1])) == {0, 2}
+
+
+# ---------------------------------------------------------------- FP64-class products from exact integer products
+def _ozaki_py(A, B, rint=round):
+    """The definition with Python integers: row exponents from frexp, entries
+    rounded to integers (round half to even by default), exact integer sums,
+    Python's correctly rounded int-to-float conversion, scaled back."""
+    import math
+
+    def exps(X):
+        out = []
+        for row in X:
+            mu = max(abs(float(v)) for v in row)
+            out.append(0 if mu == 0 else 53 - math.frexp(mu)[1])
+        return out
+
+    ea, eb = exps(A), exps(B)
+    ia = [[int(rint(math.ldexp(float(v), e))) for v in row] for row, e in zip(A, ea)]
+    ib = [[int(rint(math.ldexp(float(v), e))) for v in row] for row, e in zip(B, eb)]
+    D = np.empty((len(A), len(B)))
+    for r in range(len(A)):
+        for s in range(len(B)):
+            P = sum(x * y for x, y in zip(ia[r], ib[s]))
+            D[r, s] = math.ldexp(float(P), -(ea[r] + eb[s]))
+    return D
+
+
+def test_ozaki_gemm_brute_force(orc):
+    """Bit for bit against the definition worked with Python integers, on
+    rows spanning 60 orders of magnitude, a zero row and mixed signs; the data
+    is discriminating: truncating instead of rounding to nearest changes it."""
+    g = synth.normal(91, 9 * 37).reshape(9, 37)
+    A = g[:5] * np.array([1.0, 1e-30, 1e30, 3.0, 0.0])[:, None]
+    A[3, ::3] *= 1e-12  # small entries inside a row: rounded relative to the row maximum
+    B = g[5:] * np.array([2.0 ** -40, 1.0, 7.0, 1e-8])[:, None]
+    D = orc.ozaki_gemm(A, B)
+    Dp = _ozaki_py(A, B)
+    assert np.array_equal(D.view(np.int64), Dp.view(np.int64))
+    assert np.all(D[4] == 0.0)
+    Dt = _ozaki_py(A, B, rint=lambda v: int(v))  # truncation toward zero: a plausible mistake
+    assert not np.array_equal(D, Dt)
+    # and the definition is close to the exact product
+    assert np.allclose(D, A @ B.T, rtol=1e-13, atol=0)
+
+
+def test_ozaki_conversion_rounds_halfway_to_even(orc):
+    """The 128-bit sum is rounded once, to nearest with ties to even: row
+    [2^52, t] times row [2, 1] scales to integers [2^52, t] and [2^52, 2^51],
+    so P = 2^104 + t 2^51 lies exactly halfway between two doubles for t = 1
+    and t = 3 (down to 2^104, up to 2^104 + 2^53), and the result is P 2^-51."""
+    for t, want in [(1.0, 2.0 ** 53), (3.0, 2.0 ** 53 + 4.0), (2.0, 2.0 ** 53 + 2.0), (5.0, 2.0 ** 53 + 4.0)]:
+        A = np.array([[2.0 ** 52, t]])
+        B = np.array([[2.0, 1.0]])
+        assert orc.ozaki_row_exp(A[0]) == 0 and orc.ozaki_row_exp(B[0]) == 51
+        D = orc.ozaki_gemm(A, B)
+        assert D[0, 0] == want, (t, D[0, 0], want)
+        assert D[0, 0] == _ozaki_py(A, B)[0, 0]
+
+
+def test_ozaki_integers_exact_and_error_bound(orc):
+    """Small integers are exact (every scaled entry is an integer and every
+    sum fits); random data stays within the bound of the definition, against
+    the exact rational product: each scaled entry moves by at most half a
+    unit, 2^-53 of its row maximum, so each term by 2 2^-53 mu_r nu_s (plus
+    a second-order part), and the sum is rounded once."""
+    from fractions import Fraction
+
+    L0 = synth.int_lower(24, 5)
+    assert np.array_equal(orc.ozaki_gemm(L0, L0), L0 @ L0.T)
+    k = 64
+    A = synth.normal(92, 6 * k).reshape(6, k) * np.logspace(-3, 3, k)
+    B = synth.normal(93, 5 * k).reshape(5, k)
+    D = orc.ozaki_gemm(A, B)
+    for r in range(6):
+        for s in range(5):
+            exact = sum(Fraction(float(A[r, c])) * Fraction(float(B[s, c])) for c in range(k))
+            bound = 2 * k * 2.0 ** -53 * np.abs(A[r]).max() * np.abs(B[s]).max() * (1 + 2.0 ** -52) \
+                + abs(float(exact)) * 2.0 ** -53
+            assert abs(Fraction(float(D[r, s])) - exact) <= Fraction(bound)
+
+
+def test_mp_factor_lo64(orc):
+    """O2 with emulated FP64-class products: exact on an integer factor for
+    every band width; on the covariance at FP64 level (backward error below
+    1e-15) and within rounding of the plain O2 for an all-FP64 map."""
+    n, b = 384, 64
+    L0 = synth.int_lower(n, 41)
+    A0 = L0 @ L0.T
+    nt = n // b
+    z = np.zeros((nt, nt), np.uint8)
+    for band in (0, 1, 3):
+        Lh, info, _ = orc.mp_factor(A0, b, z, lo64=1, band=band)
+        assert info == 0 and np.array_equal(Lh, L0)
+    L = 20
+    sigma, x = synth.workload(L)
+    S = orc.cov_dense(sigma, x, 5.0, 1e-8)
+    m = np.zeros((7, 7), np.uint8)
+    L1, i1, _ = orc.mp_factor(S, 64, m, lo64=1, band=0)
+    L2, i2, _ = orc.mp_factor(S, 64, m, lo64=0)
+    assert i1 == 0 and i2 == 0
+    assert orc.backward_error(S, L1) <= 1e-15
+    assert np.linalg.norm(L1 - L2) <= 1e-12 * np.linalg.norm(L2)
+    # the emulated products do not depend on the summation order: only the
+    # FP64 sums of SYRK differ between the two orders
+    L3, _, _ = orc.mp_factor(S, 64, m, lo64=1, band=0, order=1)
+    assert np.linalg.norm(L3 - L1) <= 1e-13 * np.linalg.norm(L1)
