@@ -206,7 +206,7 @@ def bench_sht(M, torch, L, T, reps, cpu):
     return out
 
 
-def bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, lo32):
+def bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, lo32, lo64):
     """The band precision variants of Sec. IV.B on the same workload, one
     untimed run then one timed run each: DP/SP (one FP64 band, the rest
     FP32), DP/SP/HP (then the narrowest band holding >= 5% of the
@@ -217,7 +217,7 @@ def bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, lo32)
     out = {}
     for v in (1, 2, 3):
         hb = M.mpchol_create(n, tile, stream=torch.cuda.current_stream(), lo16=cfg["lo16"], allowed=cfg["allowed"],
-                             band_variant=v, lo32=lo32)
+                             band_variant=v, lo32=lo32, lo64=lo64)
         try:
             ts = []
             for r in range(2):
@@ -256,6 +256,9 @@ def main():
     ap.add_argument("--eps", type=float, default=None, help="override the workload's accuracy threshold")
     ap.add_argument("--lo32", default="bf16x3", choices=["fp32", "bf16x3"],
                     help="FP32-class update arithmetic: FP32 MFMA or three-way BF16 split products")
+    ap.add_argument("--lo64", default="fp64", choices=["fp64", "int8"],
+                    help="FP64-class update products beyond the FP64 band: FP64 MFMA, or exact integer products "
+                         "from INT8 residues (the plain FP64 comparison path always uses the FP64 MFMA)")
     ap.add_argument("--band-variant", type=int, default=None, choices=[1, 2, 3],
                     help="band rule variant: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP")
     ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
@@ -330,6 +333,7 @@ def main():
     need_w = (args.rule or "").startswith("learned") or "learned" in args.compare
     extra = {} if args.band_variant is None else {"band_variant": args.band_variant}
     extra["lo32"] = M.LO32_BF16X3 if args.lo32 == "bf16x3" else M.LO32_FP32
+    extra["lo64"] = M.LO64_INT8 if args.lo64 == "int8" else M.LO64_FP64
     h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
                         verify=2 if need_w else 0, verify_eps=eps, **extra)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
@@ -459,7 +463,7 @@ def main():
     M.mpchol_destroy(h)
     band = None
     if not args.no_band and args.config in ("c3", "c4"):
-        band = bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, extra["lo32"])
+        band = bench_band(M, torch, n, tile, cfg, sigma, x, rho, nugget, flops, fp64, extra["lo32"], extra["lo64"])
     sht = None
     if args.sht > 0:
         sht = bench_sht(M, torch, args.sht, sht_T, max(args.steps, 1), False)
@@ -474,12 +478,14 @@ def main():
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if rule == M.RULE_FP64 else "f64/" + ("bf16x3-f32acc" if args.lo32 == "bf16x3" else "f32") + "/" +
+        "dtype": "f64" if rule == M.RULE_FP64 else ("f64+int8crt" if args.lo64 == "int8" else "f64") + "/" +
+                 ("bf16x3-f32acc" if args.lo32 == "bf16x3" else "f32") + "/" +
                  ("bf16" if cfg["lo16"] else "f16") + ("/fp8-e4m3" if cfg["allowed"] & 8 else ""),
         "data": "synthetic",
         "config": {"workload": f"SH covariance L={L} (N={n}), tile {tile}, rho={rho}, nugget 1e-8, "
                                f"{[k for k, v in RULES.items() if v == rule][0]} rule eps={eps}, classes {cfg['label']}",
                    "N": n, "tile": tile, "nt": nt, "rho": rho, "eps": eps, "fp32_class": args.lo32,
+                   "fp64_class": args.lo64,
                    "step": "generate+norms+map+factor+logdet" + ("+1000 draws" if cfg["draws"] else "")
                            + (f"+solve({cfg['rhs']} rhs)" if cfg["rhs"] else "")},
         "t_factor_ms": round(t_med, 2),
@@ -502,6 +508,9 @@ def main():
         "gemm_tflops": {CLASS[c]: round(st["gemm_flops"][c] / st["t_gemm_ms"][c] / 1e9, 2)
                         for c in range(4) if st["t_gemm_ms"][c] > 0},
         "gemm_ms": {CLASS[c]: round(st["t_gemm_ms"][c], 1) for c in range(4)},
+        "gemm_fp64_int8": None if not st["gemm_int8_launches"] else
+        {"ms": round(st["t_gemm_int8_ms"], 1), "launches": st["gemm_int8_launches"],
+         "tflops_fp64_equivalent": round(st["gemm_int8_flops"] / st["t_gemm_int8_ms"] / 1e9, 2)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "context": "paper: 0.976 EFlop/s DP/HP on 9,025 Frontier nodes (36,100 MI250X), multi-node; not comparable",

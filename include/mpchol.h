@@ -56,6 +56,9 @@ extern "C" {
 #define MPCHOL_LO16_BF16 1
 #define MPCHOL_LO32_FP32 0
 #define MPCHOL_LO32_BF16X3 1
+/* how FP64-class tile products are formed */
+#define MPCHOL_LO64_FP64 0 /* on the FP64 MFMA */
+#define MPCHOL_LO64_INT8 1 /* exact integer products from INT8 residues (see mpchol_opts.lo64) */
 
 /* precision-map rules */
 #define MPCHOL_RULE_FP64 0    /* every tile FP64 (the plain FP64 path) */
@@ -86,6 +89,16 @@ typedef struct mpchol_opts {
                             MPCHOL_LO32_BF16X3 (each FP32 operand split into three BF16 parts, the six
                             significant part products on the BF16 MFMA, FP32 accumulation); storage,
                             conversion and the map rule are the same for both; default BF16X3 */
+    int32_t lo64;        /* arithmetic of the FP64-class GEMM updates of tiles farther than `band` from the
+                            diagonal under a mixed rule (NORM, BAND, USER, LEARNED): MPCHOL_LO64_FP64 (FP64
+                            MFMA) or MPCHOL_LO64_INT8 -- the Ozaki scheme II (Ozaki, Uchino and Imamura):
+                            each row of an FP64 panel copy scaled by 2^e so that its maximum lies in
+                            [2^52, 2^53) and rounded to integers (ties to even), the integer product formed
+                            exactly from INT8 MFMA products modulo 15 coprime moduli <= 256 and the Chinese
+                            remainder theorem, rounded once to FP64 and scaled back; the FP64 work tile
+                            accumulates as before.  SYRK, the tiles within `band` and the plain FP64 path
+                            (rule FP64) stay on the FP64 MFMA.  Tiles up to 1024 (else MPCHOL_EUNSUPPORTED
+                            at create); needs 4 NT tile^2 15 bytes more panel memory.  Default FP64. */
 } mpchol_opts;
 
 typedef struct mpchol_stats {
@@ -105,6 +118,9 @@ typedef struct mpchol_stats {
     double verify_first;         /* backward error (exact or estimated) of the first map verify judged;
                                     +inf if that map's factorization broke down; -1 if no map was verified */
     double t_samples_ms;         /* last set_samples: the covariance product (ms) */
+    double t_gemm_int8_ms;       /* profile mode: FP64-class update launches formed from INT8 products (lo64) */
+    int64_t gemm_int8_launches;
+    double gemm_int8_flops;      /* their task flops (2b^3 per item and step) */
 } mpchol_stats;
 
 /* Default options: device 0, null stream, FP16, band 1, all classes allowed. */

@@ -29,8 +29,8 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-ta
          "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form", "-I", os.path.join(ROOT, "include"),
          "-Wno-unused-result"]
 
-SOURCES = ["k_tiles.hip", "k_factor.hip", "k_residual.hip", "k_estimate.hip", "k_apply.hip", "k_mlp.hip",
-           "k_samples.hip", "k_sht.hip", "mpchol.cpp"]
+SOURCES = ["k_tiles.hip", "k_factor.hip", "k_ozaki.hip", "k_residual.hip", "k_estimate.hip", "k_apply.hip",
+           "k_mlp.hip", "k_samples.hip", "k_sht.hip", "mpchol.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -38,6 +38,8 @@ struct Panel {
     unsigned long long *pmax;  // nt: max |X| of the TRSM output of tile I (FP64 bits)
     int32_t *pscale;           // nt*4: scale exponent of the class-q copy of tile I
     uint16_t *p32s;            // lo32 split: hi, mid, lo BF16 parts of the FP32 copy, each b*b row-major
+    int8_t *poz = nullptr;     // lo64 INT8: per tile 15 residue planes of b*b bytes, row-major
+    int32_t *pexp = nullptr;   // lo64 INT8: per tile b row exponents
 };
 
 // ---- tiles (k_tiles.hip)
@@ -58,6 +60,15 @@ void launch_trsm_panel(const Tiles &T, const Panel &P, int k, hipStream_t st);
 // small: block shapes that fit beside running update blocks.
 void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const int32_t *items, int nitems,
                    hipStream_t st, bool small);
+
+// ---- FP64-class updates from INT8 products (k_ozaki.hip)
+struct OzakiConst;
+void ozaki_const_init(OzakiConst *k);
+// sender side of step k for panel tiles with qmask bit 4: row exponents and residue planes
+void launch_ozaki_convert(const Tiles &T, const Panel &P, int k, const uint8_t *qmask, const OzakiConst *K,
+                          hipStream_t st);
+void launch_ozaki_update(const Tiles &T, const Panel &P, const Panel *P2, const int32_t *items, int nitems,
+                         const OzakiConst *K, hipStream_t st);
 
 // ---- residual (k_residual.hip): items = every lower tile as (I << 16 | J);
 // partial = scratch of nitems * (b/128)^2 doubles; tile_res2 = nt*nt output

@@ -15,6 +15,7 @@
 #include "../../include/mpchol.h"
 #include "common.h"
 #include "launch.h"
+#include "ozaki_crt.h"
 
 using namespace mpc;
 
@@ -58,6 +59,9 @@ struct mpchol_handle {
     uint8_t *p8 = nullptr;
     unsigned long long *pmax = nullptr;
     int32_t *pscale = nullptr;
+    int8_t *poz = nullptr;       // lo64 INT8: residue planes of the FP64 copies, four sets
+    int32_t *pexp = nullptr;     // lo64 INT8: their row exponents
+    OzakiConst *d_ozc = nullptr; // lo64 INT8: moduli and reconstruction constants (device)
     // per-tile metadata
     uint8_t *d_map = nullptr;
     int32_t *d_tscale = nullptr;
@@ -72,6 +76,9 @@ struct mpchol_handle {
     int32_t *d_items = nullptr;
     // (npair * 12 + 1) offsets: pair p (columns 2p, 2p+1), class, part
     // (0: column 2p+1 by column 2p; 1: columns 2p+2, 2p+3 by the pair; 2: the rest by the pair)
+    // update classes of the schedule: the four map classes, and FP64-class
+    // tiles beyond the band whose products are formed from INT8 products (lo64)
+    static constexpr int NQ = 5;
     std::vector<int64_t> item_off;
     std::vector<int32_t> item_syrk;  // per (pair, class, part): how many of its items are SYRK (I == J)
     uint8_t *d_qmask = nullptr;
@@ -126,6 +133,8 @@ struct mpchol_handle {
         P.p8 = p8 + set * nt * bb;
         P.pmax = pmax + set * nt;
         P.pscale = pscale + set * nt * 4;
+        P.poz = poz ? poz + (size_t)set * nt * OZ_NMOD * bb : nullptr;
+        P.pexp = pexp ? pexp + (size_t)set * nt * b : nullptr;
         return P;
     }
 };
@@ -198,6 +207,7 @@ static int dalloc(T **p, size_t bytes)
 static void release(mpchol_handle *h)
 {
     void *ptrs[] = {h->slots, h->orig, h->d_sigma, h->d_x, h->p64, h->p32, h->p32s, h->p16, h->p8, h->pmax, h->pscale,
+                    h->poz, h->pexp, h->d_ozc,
                     h->d_map, h->d_tscale, h->d_fro2, h->d_amax, h->d_info, h->d_scalar, h->d_items, h->d_qmask,
                     h->d_all_items, h->d_partial, h->d_tres2, h->d_params, h->d_feats, h->d_est, h->d_zbuf};
     for (void *p : ptrs)
@@ -226,6 +236,7 @@ void mpchol_default_opts(mpchol_opts *o)
     o->verify_eps = 1e-9;
     o->profile = 0;
     o->lo32 = MPCHOL_LO32_BF16X3;
+    o->lo64 = MPCHOL_LO64_FP64;
 }
 
 const char *mpchol_last_error(void) { return g_last_error; }
@@ -257,6 +268,8 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     else mpchol_default_opts(&opt);
     if (opt.lo16 != MPCHOL_LO16_F16 && opt.lo16 != MPCHOL_LO16_BF16) return MPCHOL_EINVAL;
     if (opt.lo32 != MPCHOL_LO32_FP32 && opt.lo32 != MPCHOL_LO32_BF16X3) return MPCHOL_EINVAL;
+    if (opt.lo64 != MPCHOL_LO64_FP64 && opt.lo64 != MPCHOL_LO64_INT8) return MPCHOL_EINVAL;
+    if (opt.lo64 == MPCHOL_LO64_INT8 && tile > OZ_MAX_TILE) return MPCHOL_EUNSUPPORTED;
     if (opt.band < 0) return MPCHOL_EINVAL;
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
@@ -290,6 +303,11 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     if (h->o.lo32 == MPCHOL_LO32_BF16X3) A(dalloc(&h->p32s, 4 * nt * bb * 3 * 2));
     A(dalloc(&h->p16, 4 * nt * bb * 2));
     A(dalloc(&h->p8, 4 * nt * bb));
+    if (h->o.lo64 == MPCHOL_LO64_INT8) {
+        A(dalloc(&h->poz, 4 * nt * OZ_NMOD * bb));
+        A(dalloc(&h->pexp, 4 * nt * (size_t)tile * 4));
+        A(dalloc(&h->d_ozc, sizeof(OzakiConst)));
+    }
     A(dalloc(&h->pmax, 4 * nt * 8));
     A(dalloc(&h->pscale, 4 * nt * 4 * 4));
     A(dalloc(&h->d_map, nt * nt));
@@ -312,6 +330,11 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     if (rc == MPCHOL_OK) H(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking), "hipStreamCreateWithFlags");
     if (rc == MPCHOL_OK) H(hipEventCreateWithFlags(&h->ev_next, hipEventDisableTiming), "hipEventCreateWithFlags");
     if (rc == MPCHOL_OK) H(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming), "hipEventCreateWithFlags");
+    if (rc == MPCHOL_OK && h->d_ozc) {
+        OzakiConst kc;
+        ozaki_const_init(&kc);
+        H(hipMemcpy(h->d_ozc, &kc, sizeof(kc), hipMemcpyHostToDevice), "hipMemcpy(ozaki constants)");
+    }
     if (rc == MPCHOL_OK) {
         std::vector<int32_t> all;
         all.reserve(h->ntile);
@@ -519,37 +542,48 @@ static void rule_band(mpchol_handle *h, std::vector<uint8_t> &m)
 // columns c+2 and c+3 (which the next pair's panel needs), part 2 the rest
 // (J >= c+4); parts 1 and 2 take both columns of the pair (K = 2b).  And, per
 // panel tile (I, k), the mask of classes its consumers use.
-static void build_schedule_counts(mpchol_handle *h, std::vector<int32_t> &items, std::vector<uint8_t> &qmask)
+// Update class of tile (I, J): its map class, except that FP64-class tiles
+// beyond the FP64 band form their products from INT8 products when lo64 asks
+// for it (class 4); SYRK, the band and the plain FP64 path stay on the FP64
+// MFMA.
+static int update_class(const mpchol_handle *h, int I, int J, bool int8_ok)
 {
-    const int nt = h->nt, npair = (nt + 1) / 2;
-    h->item_off.assign((size_t)npair * 12 + 1, 0);
-    h->item_syrk.assign((size_t)npair * 12, 0);
+    if (I == J) return P64;
+    const int cl = h->h_map[I + (size_t)J * h->nt];
+    if (cl == P64 && int8_ok && I - J > h->o.band) return 4;
+    return cl;
+}
+
+static void build_schedule_counts(mpchol_handle *h, std::vector<int32_t> &items, std::vector<uint8_t> &qmask,
+                                  bool int8_ok)
+{
+    const int nt = h->nt, npair = (nt + 1) / 2, NQ = mpchol_handle::NQ;
+    h->item_off.assign((size_t)npair * NQ * 3 + 1, 0);
+    h->item_syrk.assign((size_t)npair * NQ * 3, 0);
     items.clear();
     for (int p = 0; p < npair; ++p) {
         const int c = 2 * p;
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < NQ; ++q)
             for (int part = 0; part < 3; ++part) {
-                const size_t o = ((size_t)p * 4 + q) * 3 + part;
+                const size_t o = ((size_t)p * NQ + q) * 3 + part;
                 h->item_off[o] = (int64_t)items.size();
                 const int jlo = part == 0 ? c + 1 : part == 1 ? c + 2 : c + 4;
                 const int jhi = part == 0 ? c + 1 : part == 1 ? c + 3 : nt - 1;
                 for (int J = jlo; J <= jhi && J < nt; ++J)
-                    for (int I = J; I < nt; ++I) {
-                        int cl = (I == J) ? P64 : h->h_map[I + (size_t)J * nt];
-                        if (cl == q) {
+                    for (int I = J; I < nt; ++I)
+                        if (update_class(h, I, J, int8_ok) == q) {
                             items.push_back((I << 16) | J);
                             h->item_syrk[o] += (I == J);
                         }
-                    }
             }
     }
-    h->item_off[(size_t)npair * 12] = (int64_t)items.size();
+    h->item_off[(size_t)npair * NQ * 3] = (int64_t)items.size();
     qmask.assign((size_t)nt * nt, 0);
     for (int k = 0; k < nt; ++k)
         for (int I = k + 1; I < nt; ++I) {
             uint8_t msk = 1;  // SYRK(I,I) reads the FP64 copy
-            for (int J = k + 1; J < I; ++J) msk |= (uint8_t)(1u << h->h_map[I + (size_t)J * nt]);
-            for (int J = I + 1; J < nt; ++J) msk |= (uint8_t)(1u << h->h_map[J + (size_t)I * nt]);
+            for (int J = k + 1; J < I; ++J) msk |= (uint8_t)(1u << update_class(h, I, J, int8_ok));
+            for (int J = I + 1; J < nt; ++J) msk |= (uint8_t)(1u << update_class(h, J, I, int8_ok));
             qmask[I + (size_t)k * nt] = msk;
         }
 }
@@ -604,7 +638,8 @@ static int apply_map(mpchol_handle *h, int rule, double eps, const uint8_t *user
     h->h_map = m;
     std::vector<int32_t> items;
     std::vector<uint8_t> qmask;
-    build_schedule_counts(h, items, qmask);
+    // the plain FP64 path (rule FP64) keeps every product on the FP64 MFMA
+    build_schedule_counts(h, items, qmask, h->o.lo64 == MPCHOL_LO64_INT8 && rule != MPCHOL_RULE_FP64);
     if (h->d_items) (void)hipFree(h->d_items);
     h->d_items = nullptr;
     if (!items.empty()) {
@@ -680,6 +715,7 @@ static int panel_step(mpchol_handle *h, const Tiles &T, const Panel &P, int k, h
     HIPCHK(hipMemsetAsync(P.pmax, 0, (size_t)h->nt * 8, st));
     launch_panel_max(T, P, k, st);
     launch_convert(T, P, k, h->d_qmask + (size_t)k * h->nt, st);
+    if (h->d_ozc) launch_ozaki_convert(T, P, k, h->d_qmask + (size_t)k * h->nt, h->d_ozc, st);
     return MPCHOL_OK;
 }
 
@@ -689,8 +725,8 @@ static int update_list(mpchol_handle *h, const Tiles &T, const Panel &P, const P
                        hipStream_t st)
 {
     const double b3 = (double)h->b * h->b * h->b;
-    for (int q = 0; q < 4; ++q) {
-        const size_t o = ((size_t)p * 4 + q) * 3 + part;
+    for (int q = 0; q < mpchol_handle::NQ; ++q) {
+        const size_t o = ((size_t)p * mpchol_handle::NQ + q) * 3 + part;
         const int64_t off = h->item_off[o];
         const int cnt = (int)(h->item_off[o + 1] - off);
         if (cnt <= 0) continue;
@@ -700,7 +736,8 @@ static int update_list(mpchol_handle *h, const Tiles &T, const Panel &P, const P
             HIPCHK(hipEventCreate(&e1));
             HIPCHK(hipEventRecord(e0, st));
         }
-        launch_update(T, P, P2, q, h->d_items + off, cnt, st, part == 0);
+        if (q == 4) launch_ozaki_update(T, P, P2, h->d_items + off, cnt, h->d_ozc, st);
+        else launch_update(T, P, P2, q, h->d_items + off, cnt, st, part == 0);
         if (h->o.profile) {
             HIPCHK(hipEventRecord(e1, st));
             h->gev.push_back(e0);
@@ -776,10 +813,19 @@ static int run_factor(mpchol_handle *h, int64_t *info)
         h->stats.gemm_launches[q] = 0;
         h->stats.gemm_flops[q] = 0;
     }
+    h->stats.t_gemm_int8_ms = 0;
+    h->stats.gemm_int8_launches = 0;
+    h->stats.gemm_int8_flops = 0;
     for (size_t i = 0; i < h->gev_class.size(); ++i) {
         float g = 0;
         HIPCHK(hipEventElapsedTime(&g, h->gev[2 * i], h->gev[2 * i + 1]));
         int q = h->gev_class[i];
+        if (q == 4) {
+            h->stats.t_gemm_int8_ms += g;
+            h->stats.gemm_int8_launches += 1;
+            h->stats.gemm_int8_flops += h->gev_flops[i];
+            continue;
+        }
         h->stats.t_gemm_ms[q] += g;
         h->stats.gemm_launches[q] += 1;
         h->stats.gemm_flops[q] += h->gev_flops[i];

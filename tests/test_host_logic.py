@@ -7,6 +7,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 import synth
 
@@ -79,3 +80,78 @@ def test_bench_solve_backward_error():
     want = np.linalg.norm(R) / (fro * np.linalg.norm(X * (1 + 1e-6)) + np.linalg.norm(B))
     got = bench.solve_backward_error(sigma, x, 5.0, 1e-8, X * (1 + 1e-6), B, fro)
     assert abs(got - want) <= 1e-6 * want
+
+
+# ---------------------------------------------------------------- residue arithmetic of the INT8-emulated FP64 products
+def _ozaki_host_check():
+    """Build (hipcc, host code) the CPU driver of the library's residue helpers."""
+    import shutil
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = os.path.join(root, "_build", "ozaki_host_check")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not shutil.which(hipcc) and not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    subprocess.check_call([hipcc, "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature",
+                           "-Xclang", "-packed-fp32-ops", os.path.join(root, "tests", "ozaki_host_check.cpp"),
+                           os.path.join(root, "paper_2408_04440_amd", "csrc", "k_ozaki.hip"), "-o", out],
+                          stderr=subprocess.DEVNULL)
+    return out
+
+
+def test_crt_reconstruction_rounds_like_python():
+    """The exact integer product recovered from its 15 residues (both exact
+    forms of the residue sum) and rounded once to FP64 equals Python's
+    correctly rounded float(P), bit for bit, for
+    random |P| < 2^116 (the bound of 1024 products of 54-bit integers),
+    halfway cases of every size, powers of two, +-1, 0 and the extremes."""
+    import random
+    import struct
+    import subprocess
+
+    exe = _ozaki_host_check()
+    rng = random.Random(2024)
+    Ps = [0, 1, -1, 2 ** 116, -(2 ** 116), 2 ** 53, 2 ** 53 + 1, -(2 ** 53 + 1), 2 ** 64 - 1, 2 ** 64, 2 ** 64 + 1]
+    for e in range(54, 117):
+        ulp = 2 ** (e - 52)
+        base = rng.randrange(2 ** 52, 2 ** 53) * ulp
+        Ps += [base + ulp // 2, -(base + ulp // 2), base + ulp // 2 + 1, base + ulp // 2 - 1, base, 2 ** e,
+               base + ulp + ulp // 2]
+    for _ in range(4000):
+        bits = rng.randrange(1, 117)
+        Ps.append(rng.randrange(-(2 ** bits), 2 ** bits))
+    lines = [f"P {1 if P < 0 else 0} {abs(P) >> 64:x} {abs(P) & (2 ** 64 - 1):x}" for P in Ps]
+    out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True).stdout.split()
+    assert len(out) == 2 * len(Ps)
+    for i, P in enumerate(Ps):
+        for h in out[2 * i:2 * i + 2]:  # four-limb sums, and the three FP64 parts the update kernel keeps
+            got = struct.unpack("<d", struct.pack("<Q", int(h, 16)))[0]
+            assert got == float(P) and (got != 0 or P == 0), (P, got, float(P))
+
+
+def test_residue_conversions():
+    """Signed residues of integer-valued doubles |a| <= 2^53 (the operands'
+    integers) and residues of INT8 product sums |x| <= 2^24, against Python."""
+    import random
+    import subprocess
+
+    exe = _ozaki_host_check()
+    rng = random.Random(7)
+    ps = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 217, 211, 199, 197]
+    cases, want = [], []
+    for _ in range(3000):
+        p = rng.choice(ps)
+        a = rng.choice([rng.randrange(-(2 ** 53), 2 ** 53 + 1), rng.randrange(-300, 300), 2 ** 53, -(2 ** 53)])
+        cases.append(f"sym {float(a)!r} {p}")
+        r = a % p
+        want.append(r - p if r >= (p + 1) // 2 else r)
+        x = rng.randrange(-(2 ** 24), 2 ** 24 + 1)
+        cases.append(f"small {x} {p}")
+        want.append(x % p)
+    out = subprocess.run([exe], input="\n".join(cases) + "\n", capture_output=True, text=True, check=True).stdout.split()
+    assert [int(v) for v in out] == want
+    for w, c in zip(want[::2], cases[::2]):
+        p = int(c.split()[-1])
+        assert -(p // 2) <= w <= (p - 1) // 2
