@@ -281,13 +281,20 @@ __global__ __launch_bounds__(64 * WM * WN) void update_cm_kernel(Tiles Tt, const
         }
 }
 
+// Up to four panel columns applied in one accumulation (the steps of one or
+// two pairs): their copies and scale exponents.
+template <typename T> struct PanelSet {
+    const T *p[4];
+    const int32_t *s[4];  // scale exponents (class q copy of tile I at s[h][I * 4 + q]); unused for the split copies
+    int n;
+};
+
 template <int KIND, int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const typename RM<KIND>::T *panel0,
-                                                                 const int32_t *pscale0,
-                                                                 const typename RM<KIND>::T *panel1,
-                                                                 const int32_t *pscale1, int q, const int32_t *items)
+__global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, PanelSet<typename RM<KIND>::T> ps, int q,
+                                                                 const int32_t *items)
 {
     typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
+    typedef typename RM<KIND>::T T;
     extern __shared__ __align__(16) char smem_raw[];
     const int b = Tt.b;
     const int tmn = b / BM, tnn = b / BN;
@@ -303,28 +310,29 @@ __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const
     for (int m = 0; m < S::MB; ++m)
 #pragma unroll
         for (int n = 0; n < S::NB; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    // Scaled copies: product = acc * 2^-(t_I + t_J).  For a pair of steps the
-    // step with the larger exponent sum (smaller values) is accumulated first
-    // and the accumulator rescaled down to the other step's exponent, which is
-    // exact and cannot overflow; the second product then adds at that scale.
-    const typename RM<KIND>::T *pa = panel0, *pb = panel1;
-    int tsum = pscale0[I * 4 + q] + pscale0[J * 4 + q];
-    int t2 = 0;
-    if (panel1) {
-        t2 = pscale1[I * 4 + q] + pscale1[J * 4 + q];
-        if (t2 > tsum) {
-            pa = panel1;
-            pb = panel0;
-            const int t = tsum;
-            tsum = t2;
-            t2 = t;
+    // Scaled copies: the product of step h is acc * 2^-(t_I + t_J) with its own
+    // exponent sum.  The steps are taken in decreasing exponent sum (smallest
+    // values first); before each later step the accumulator is rescaled down
+    // to that step's exponent sum, which is exact and cannot overflow, and
+    // the step's product then adds at that scale.
+    int ord[4], ts[4];
+    for (int h = 0; h < ps.n; ++h) {
+        const int t = ps.s[h][I * 4 + q] + ps.s[h][J * 4 + q];
+        int pos = h;
+        while (pos > 0 && ts[pos - 1] < t) {  // insertion by decreasing t (stable)
+            ts[pos] = ts[pos - 1];
+            ord[pos] = ord[pos - 1];
+            --pos;
         }
+        ts[pos] = t;
+        ord[pos] = h;
     }
-    const int npan = pb ? 2 : 1;
+    int tsum = ts[0];
 #pragma nounroll
-    for (int h = 0; h < npan; ++h) {
-        const typename RM<KIND>::T *pn = h ? pb : pa;
+    for (int h = 0; h < ps.n; ++h) {
+        const T *pn = ps.p[ord[h]];
         if (h) {
+            const int t2 = ts[h];
 #pragma unroll
             for (int m = 0; m < S::MB; ++m)
 #pragma unroll
@@ -355,11 +363,12 @@ __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, const
 // (hi,lo), (lo,hi), (hi,mid), (mid,hi), (hi,hi), smallest first, each over
 // the full K on the BF16 MFMA with FP32 accumulation; the three products
 // below a float rounding of the result -- (mid,lo), (lo,mid), (lo,lo) -- are
-// dropped.  For a pair of steps the two panels' products of one kind follow
-// each other.  Operands: panel + I*3*b*b + part*b*b, row-major b x b.
+// dropped.  For several steps (a pair, or two pairs) the panels' products of
+// one kind follow each other.  Operands: panel + I*3*b*b + part*b*b,
+// row-major b x b.
 template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void update_split_kernel(Tiles Tt, const uint16_t *panel0,
-                                                                    const uint16_t *panel1, const int32_t *items)
+__global__ __launch_bounds__(64 * WM * WN) void update_split_kernel(Tiles Tt, PanelSet<uint16_t> ps,
+                                                                    const int32_t *items)
 {
     typedef RMShape<RM_BF16, BM, BN, BK, WM, WN> S;
     extern __shared__ __align__(16) char smem_raw[];
@@ -377,13 +386,13 @@ __global__ __launch_bounds__(64 * WM * WN) void update_split_kernel(Tiles Tt, co
     for (int m = 0; m < S::MB; ++m)
 #pragma unroll
         for (int n = 0; n < S::NB; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    const int npan = panel1 ? 2 : 1;
+    const int npan = ps.n;
 #pragma nounroll
     for (int s = 0; s < 6 * npan; ++s) {
         const int t = s / npan;                      // kind of product, smallest first
         const int pa = (0x010201 >> (4 * t)) & 0xF;  // part of the I operand: 1 0 2 0 1 0
         const int pb = (0x001021 >> (4 * t)) & 0xF;  // part of the J operand: 1 2 0 1 0 0
-        const uint16_t *pn = (s % npan) ? panel1 : panel0;
+        const uint16_t *pn = ps.p[s % npan];
         rm_block<RM_BF16, BM, BN, BK, WM, WN>(pn + I * bb3 + pa * bb + (int64_t)tm * BM * b, b,
                                               pn + J * bb3 + pb * bb + (int64_t)tn * BN * b, b, b, acc,
                                               (uint8_t *)smem_raw);
@@ -403,8 +412,8 @@ __global__ __launch_bounds__(64 * WM * WN) void update_split_kernel(Tiles Tt, co
 }
 
 template <int BM, int BN, int BK, int WM, int WN>
-static void launch_split(const Tiles &T_, const uint16_t *panel0, const uint16_t *panel1, const int32_t *items,
-                         int nitems, hipStream_t st)
+static void launch_split(const Tiles &T_, const PanelSet<uint16_t> &ps, const int32_t *items, int nitems,
+                         hipStream_t st)
 {
     typedef RMShape<RM_BF16, BM, BN, BK, WM, WN> S;
     auto k = update_split_kernel<BM, BN, BK, WM, WN>;
@@ -414,7 +423,7 @@ static void launch_split(const Tiles &T_, const uint16_t *panel0, const uint16_t
         attr = true;
     }
     const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
-    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel0, panel1, items);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, ps, items);
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
@@ -433,8 +442,7 @@ static void launch_cm(const Tiles &T_, const T *panel0, const T *panel1, const i
 }
 
 template <int KIND, int BM, int BN, int BK, int WM, int WN>
-static void launch_rm(const Tiles &T_, const typename RM<KIND>::T *panel0, const int32_t *pscale0,
-                      const typename RM<KIND>::T *panel1, const int32_t *pscale1, int q, const int32_t *items,
+static void launch_rm(const Tiles &T_, const PanelSet<typename RM<KIND>::T> &ps, int q, const int32_t *items,
                       int nitems, hipStream_t st)
 {
     typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
@@ -445,28 +453,33 @@ static void launch_rm(const Tiles &T_, const typename RM<KIND>::T *panel0, const
         attr = true;
     }
     const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
-    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel0, pscale0, panel1, pscale1, q, items);
+    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, ps, q, items);
 }
 
 // Block shapes per class from a sweep on MI355X (1024 x 1024 tiles):
 // FP64 128 x 128 with 16 waves of 32 x 32, FP32 256 x 128 with 8 waves,
 // FP16/BF16 256 x 256 with 16 waves, FP8 128 x 128 with 4 waves; tiles of
 // 128 fall back to 128 x 128 blocks.
-void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const int32_t *items, int nitems,
+void launch_update(const Tiles &T, const Panel *const *Ps, int npan, int q, const int32_t *items, int nitems,
                    hipStream_t st, bool small)
 {
-    if (nitems <= 0) return;
+    if (nitems <= 0 || npan < 1 || npan > 4) return;
     // "small": a launch beside the running updates (the look-ahead stream)
     // uses block shapes whose LDS fits in the slot one finished update block
     // frees; a 1024-thread block with 147 KB of LDS would wait for a whole
     // idle compute unit.
     const bool big = (T.b % 256) == 0 && !small;
+    const Panel &P = *Ps[0];
+    const Panel *P2 = npan > 1 ? Ps[1] : nullptr;  // the FP64 / FP32-MFMA updates take one pair at most
     switch (q) {
     case P64: launch_cm<double, 128, 128, 16, 4, 4>(T, P.p64, P2 ? P2->p64 : nullptr, items, nitems, st); break;
     case P32:
         if (T.lo32) {
-            if (big) launch_split<256, 256, 64, 4, 4>(T, P.p32s, P2 ? P2->p32s : nullptr, items, nitems, st);
-            else launch_split<128, 128, 64, 2, 2>(T, P.p32s, P2 ? P2->p32s : nullptr, items, nitems, st);
+            PanelSet<uint16_t> ps{};
+            ps.n = npan;
+            for (int h = 0; h < npan; ++h) ps.p[h] = Ps[h]->p32s;
+            if (big) launch_split<256, 256, 64, 4, 4>(T, ps, items, nitems, st);
+            else launch_split<128, 128, 64, 2, 2>(T, ps, items, nitems, st);
         } else if ((T.b % 256) == 0) {
             launch_cm<float, 256, 128, 16, 4, 2>(T, P.p32, P2 ? P2->p32 : nullptr, items, nitems, st);
         } else {
@@ -474,21 +487,31 @@ void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const
         }
         break;
     case P16: {
-        const uint16_t *p2 = P2 ? P2->p16 : nullptr;
-        const int32_t *s2 = P2 ? P2->pscale : nullptr;
+        PanelSet<uint16_t> ps{};
+        ps.n = npan;
+        for (int h = 0; h < npan; ++h) {
+            ps.p[h] = Ps[h]->p16;
+            ps.s[h] = Ps[h]->pscale;
+        }
         if (T.lo16 == LO16_BF16) {
-            if (big) launch_rm<RM_BF16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
-            else launch_rm<RM_BF16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
+            if (big) launch_rm<RM_BF16, 256, 256, 64, 4, 4>(T, ps, q, items, nitems, st);
+            else launch_rm<RM_BF16, 128, 128, 64, 2, 2>(T, ps, q, items, nitems, st);
         } else {
-            if (big) launch_rm<RM_F16, 256, 256, 64, 4, 4>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
-            else launch_rm<RM_F16, 128, 128, 64, 2, 2>(T, P.p16, P.pscale, p2, s2, q, items, nitems, st);
+            if (big) launch_rm<RM_F16, 256, 256, 64, 4, 4>(T, ps, q, items, nitems, st);
+            else launch_rm<RM_F16, 128, 128, 64, 2, 2>(T, ps, q, items, nitems, st);
         }
         break;
     }
-    default:
-        launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, P.p8, P.pscale, P2 ? P2->p8 : nullptr, P2 ? P2->pscale : nullptr, q,
-                                               items, nitems, st);
+    default: {
+        PanelSet<uint8_t> ps{};
+        ps.n = npan;
+        for (int h = 0; h < npan; ++h) {
+            ps.p[h] = Ps[h]->p8;
+            ps.s[h] = Ps[h]->pscale;
+        }
+        launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, ps, q, items, nitems, st);
         break;
+    }
     }
 }
 

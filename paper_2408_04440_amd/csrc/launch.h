@@ -55,10 +55,10 @@ void launch_zero_upper_diag(const Tiles &T, int k, hipStream_t st);
 // ---- factorization (k_factor.hip)
 void launch_potrf_tile(const Tiles &T, int k, unsigned long long *info, hipStream_t st);
 void launch_trsm_panel(const Tiles &T, const Panel &P, int k, hipStream_t st);
-// grouped update A_IJ -= L_Ik L_Jk^T of class q over `nitems` packed (I << 16 | J) items
-// P2 (optional): the next step's panel; the update then covers both steps.
+// grouped update A_IJ -= sum_h L_I,k_h L_J,k_h^T of class q over `nitems` packed (I << 16 | J)
+// items from the npan panels Ps[0..npan-1] (npan <= 2 for FP64 and FP32-MFMA, <= 4 otherwise);
 // small: block shapes that fit beside running update blocks.
-void launch_update(const Tiles &T, const Panel &P, const Panel *P2, int q, const int32_t *items, int nitems,
+void launch_update(const Tiles &T, const Panel *const *Ps, int npan, int q, const int32_t *items, int nitems,
                    hipStream_t st, bool small);
 
 // ---- FP64-class updates from INT8 products (k_ozaki.hip)

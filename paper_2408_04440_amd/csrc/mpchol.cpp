@@ -23,6 +23,11 @@ namespace {
 
 enum State { S_CREATED = 0, S_SOURCE = 1, S_LOADED = 2, S_FACTORED = 3, S_FAILED = 4 };
 
+// Panel copy sets, indexed by panel column mod NSET: the two pairs whose
+// low-class updates are applied together, and the pair the look-ahead
+// stream is factoring.
+constexpr int NSET = 6;
+
 double unit_roundoff(int q, int lo16)
 {
     switch (q) {
@@ -298,18 +303,18 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
         if (rc == MPCHOL_OK && r != MPCHOL_OK) rc = r;
     };
     A(dalloc(&h->slots, h->ntile * h->slot_bytes));
-    A(dalloc(&h->p64, 4 * nt * bb * 8));
-    A(dalloc(&h->p32, 4 * nt * bb * 4));
-    if (h->o.lo32 == MPCHOL_LO32_BF16X3) A(dalloc(&h->p32s, 4 * nt * bb * 3 * 2));
-    A(dalloc(&h->p16, 4 * nt * bb * 2));
-    A(dalloc(&h->p8, 4 * nt * bb));
+    A(dalloc(&h->p64, NSET * nt * bb * 8));
+    A(dalloc(&h->p32, NSET * nt * bb * 4));
+    if (h->o.lo32 == MPCHOL_LO32_BF16X3) A(dalloc(&h->p32s, NSET * nt * bb * 3 * 2));
+    A(dalloc(&h->p16, NSET * nt * bb * 2));
+    A(dalloc(&h->p8, NSET * nt * bb));
     if (h->o.lo64 == MPCHOL_LO64_INT8) {
-        A(dalloc(&h->poz, 4 * nt * OZ_NMOD * bb));
-        A(dalloc(&h->pexp, 4 * nt * (size_t)tile * 4));
+        A(dalloc(&h->poz, NSET * nt * OZ_NMOD * bb));
+        A(dalloc(&h->pexp, NSET * nt * (size_t)tile * 4));
         A(dalloc(&h->d_ozc, sizeof(OzakiConst)));
     }
-    A(dalloc(&h->pmax, 4 * nt * 8));
-    A(dalloc(&h->pscale, 4 * nt * 4 * 4));
+    A(dalloc(&h->pmax, NSET * nt * 8));
+    A(dalloc(&h->pscale, NSET * nt * 4 * 4));
     A(dalloc(&h->d_map, nt * nt));
     A(dalloc(&h->d_tscale, nt * nt * 4));
     A(dalloc(&h->d_fro2, nt * nt * 8));
@@ -719,33 +724,59 @@ static int panel_step(mpchol_handle *h, const Tiles &T, const Panel &P, int k, h
     return MPCHOL_OK;
 }
 
-// The update list (pair p, part) per class on stream st; P2 is the pair's
-// second panel column (null for part 0 or a single-column pair).
-static int update_list(mpchol_handle *h, const Tiles &T, const Panel &P, const Panel *P2, int p, int part,
-                       hipStream_t st)
+// Classes whose updates an even pair leaves for the next pair beyond its
+// next panel: the FP16/BF16 and FP8 updates, so that each of their FP32 work
+// tiles is read and written once per four steps.  Their error comes from the
+// 16-bit/8-bit operands, far above the FP32 accumulation over K = 4b; the
+// FP32 class, whose error is that accumulation's, keeps K = 2b.
+static bool deferred_class(const mpchol_handle *, int q) { return q == P16 || q == P8; }
+
+// The update list (pair p, part) per class on stream st.  P holds the panel
+// sets by column mod NSET; c = 2p.  Part 0: column c+1 by column c.  Parts 1
+// and 2: the pair's two columns, except for the deferred classes: an even
+// pair skips their part 2, and an odd pair applies both pairs (columns c-2
+// .. c+1) to its parts 1 and 2 of those classes.
+static int update_list(mpchol_handle *h, const Tiles &T, const Panel *P, int p, int part, hipStream_t st)
 {
     const double b3 = (double)h->b * h->b * h->b;
+    const int c = 2 * p;
     for (int q = 0; q < mpchol_handle::NQ; ++q) {
         const size_t o = ((size_t)p * mpchol_handle::NQ + q) * 3 + part;
         const int64_t off = h->item_off[o];
         const int cnt = (int)(h->item_off[o + 1] - off);
         if (cnt <= 0) continue;
+        const Panel *ps[4];
+        int npan = 0;
+        if (part == 0) {
+            ps[npan++] = &P[c % NSET];
+        } else if (q < 4 && deferred_class(h, q)) {
+            if ((p & 1) == 0 && part == 2) continue;  // left for the next pair
+            if (p & 1) {
+                ps[npan++] = &P[(c - 2) % NSET];
+                ps[npan++] = &P[(c - 1) % NSET];
+            }
+            ps[npan++] = &P[c % NSET];
+            ps[npan++] = &P[(c + 1) % NSET];
+        } else {
+            ps[npan++] = &P[c % NSET];
+            ps[npan++] = &P[(c + 1) % NSET];
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (h->o.profile) {
             HIPCHK(hipEventCreate(&e0));
             HIPCHK(hipEventCreate(&e1));
             HIPCHK(hipEventRecord(e0, st));
         }
-        if (q == 4) launch_ozaki_update(T, P, P2, h->d_items + off, cnt, h->d_ozc, st);
-        else launch_update(T, P, P2, q, h->d_items + off, cnt, st, part == 0);
+        if (q == 4) launch_ozaki_update(T, *ps[0], npan > 1 ? ps[1] : nullptr, h->d_items + off, cnt, h->d_ozc, st);
+        else launch_update(T, ps, npan, q, h->d_items + off, cnt, st, part == 0);
         if (h->o.profile) {
             HIPCHK(hipEventRecord(e1, st));
             h->gev.push_back(e0);
             h->gev.push_back(e1);
             h->gev_class.push_back(q);
-            // task flops of the launch per step: GEMM 2b^3, SYRK b^3 (its kernel computes the lower blocks only)
+            // task flops of the launch: per step GEMM 2b^3, SYRK b^3 (its kernel computes the lower blocks only)
             const int syrk = h->item_syrk[o];
-            h->gev_flops.push_back(b3 * (2.0 * (cnt - syrk) + syrk) * (P2 ? 2 : 1));
+            h->gev_flops.push_back(b3 * (2.0 * (cnt - syrk) + syrk) * npan);
         }
     }
     return MPCHOL_OK;
@@ -759,25 +790,27 @@ static int panel_pair(mpchol_handle *h, const Tiles &T, const Panel *P, int c, h
     const int nt = h->nt;
     launch_potrf_tile(T, c, h->d_info, st);
     if (c + 1 >= nt) return MPCHOL_OK;
-    int rc = panel_step(h, T, P[c % 4], c, st);
+    int rc = panel_step(h, T, P[c % NSET], c, st);
     if (rc) return rc;
-    rc = update_list(h, T, P[c % 4], nullptr, c / 2, 0, st);
+    rc = update_list(h, T, P, c / 2, 0, st);
     if (rc) return rc;
     launch_potrf_tile(T, c + 1, h->d_info, st);
-    if (c + 2 < nt) rc = panel_step(h, T, P[(c + 1) % 4], c + 1, st);
+    if (c + 2 < nt) rc = panel_step(h, T, P[(c + 1) % NSET], c + 1, st);
     return rc;
 }
 
 // Right-looking tile algorithm taken two steps at a time, with look-ahead:
 // the caller's stream A applies pair (c, c+1) to the trailing tiles with
-// K = 2b; once columns c+2 and c+3 are updated, a second stream B runs the
-// next pair's panel work (into the other two panel sets) while A finishes the
-// rest of the pair's update.
+// K = 2b (the deferred classes: K = 4b every other pair); once columns c+2
+// and c+3 are updated, a second stream B runs the next pair's panel work
+// (into its own two panel sets) while A finishes the rest of the pair's
+// update.
 static int run_factor(mpchol_handle *h, int64_t *info)
 {
     const int nt = h->nt;
     Tiles T = h->tiles();
-    const Panel P[4] = {h->panel(0), h->panel(1), h->panel(2), h->panel(3)};
+    Panel P[NSET];
+    for (int i = 0; i < NSET; ++i) P[i] = h->panel(i);
     hipStream_t A = h->st, B = h->st2;
     for (auto e : h->gev) (void)hipEventDestroy(e);
     h->gev.clear();
@@ -788,15 +821,14 @@ static int run_factor(mpchol_handle *h, int64_t *info)
     int rc = panel_pair(h, T, P, 0, A);
     if (rc) return rc;
     for (int c = 0; c + 2 < nt; c += 2) {
-        const Panel &P0 = P[c % 4], *P1 = &P[(c + 1) % 4];
-        rc = update_list(h, T, P0, P1, c / 2, 1, A);
+        rc = update_list(h, T, P, c / 2, 1, A);
         if (rc) return rc;
         HIPCHK(hipEventRecord(h->ev_next, A));
         HIPCHK(hipStreamWaitEvent(B, h->ev_next, 0));
         rc = panel_pair(h, T, P, c + 2, B);
         if (rc) return rc;
         HIPCHK(hipEventRecord(h->ev_panel, B));
-        rc = update_list(h, T, P0, P1, c / 2, 2, A);
+        rc = update_list(h, T, P, c / 2, 2, A);
         if (rc) return rc;
         HIPCHK(hipStreamWaitEvent(A, h->ev_panel, 0));
     }
