@@ -28,6 +28,7 @@ __device__ inline void wave_sync()
 __global__ __launch_bounds__(64) void potrf_block_kernel(double *tile, int b, int j0, int64_t col0, int64_t n,
                                                          unsigned long long *info)
 {
+    __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
     __shared__ double a[64][65];
     const int r = threadIdx.x;
     double *base = tile + j0 + (int64_t)j0 * b;
@@ -75,6 +76,7 @@ constexpr int TPAD = 4;
 __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, const double *L, int64_t ldl, int nL,
                                                    double *xin, int64_t ldin, int mode)
 {
+    __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
     __shared__ double xs[32][64 + TPAD];  // X chunk: xs[k][row]
     __shared__ double ls[32][32 + TPAD];  // L chunk: ls[k][c] = L(cb + c, k0 + k)
     __shared__ double ts[32][64 + 1];     // right-hand side / solution: ts[c][row]
@@ -175,6 +177,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
 // C -= X X^T on the lower 64 x 64 blocks of an M x M FP64 block (K = 64).
 __global__ __launch_bounds__(256) void syrk_tile_kernel(const double *X, double *Cm, int b, int nblk)
 {
+    __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
     extern __shared__ __align__(16) char smem_raw[];
     // block (bi, bj), bi >= bj, from the linear index
     int t = blockIdx.x;

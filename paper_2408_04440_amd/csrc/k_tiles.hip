@@ -92,6 +92,7 @@ __global__ __launch_bounds__(256) void copy_matrix_kernel(Tiles T, const double 
 // non-negative values order like unsigned integers).
 __global__ __launch_bounds__(256) void panel_max_kernel(Tiles T, Panel P, int k)
 {
+    __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
     __shared__ double sm[256];
     const int I = k + 1 + blockIdx.y;
     const int64_t bb = (int64_t)T.b * T.b;
@@ -117,6 +118,7 @@ __global__ __launch_bounds__(256) void panel_max_kernel(Tiles T, Panel P, int k)
 // own scale (row-major for the 16-bit, 8-bit and split copies).
 __global__ __launch_bounds__(256) void convert_kernel(Tiles T, Panel P, int k, const uint8_t *qmask)
 {
+    __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
     __shared__ double xs[64][65];  // xs[c][r]
     const int b = T.b, nsub = b / 64;
     const int I = k + 1 + blockIdx.y;
