@@ -300,14 +300,15 @@ int mpchol_selector_features(mpchol_t h, double eps, float *feats);
  * residual) while the total stays within (eps ||S||_F)^2 / 2, then verify
  * with one factorization and raise the worst tiles until it holds (at most
  * 64 rounds; after a breakdown the tiles are ranked by the residual measured
- * for their class).  The greedy weighs a tile's time by the per-class update
- * rates of the FP64, FP32, 16-bit and FP8 kernels at the headline size
- * (58, 130, 600, 700 TFLOP/s).  labels: host NT x NT uint8 (the resulting
- * map); *berr_out its measured backward error (+inf after a breakdown).
- * MPCHOL_EBUDGET if no round met the budget (labels then hold the last map
- * tried).  The handle must have a matrix set; its tiles are reloaded and
- * refactored several times. */
-int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out);
+ * for their class).  The greedy weighs a tile's time by the update rate of
+ * each class (FP64, FP32, 16-bit, FP8): rates (optional host double[4],
+ * TFLOP/s, all > 0), else those of this library's update kernels inside the
+ * factorization at N = 129,600 (61, 168, 770, 850).  labels: host NT x NT
+ * uint8 (the resulting map); *berr_out its measured backward error (+inf
+ * after a breakdown).  MPCHOL_EBUDGET if no round met the budget (labels
+ * then hold the last map tried).  The handle must have a matrix set; its
+ * tiles are reloaded and refactored several times. */
+int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out, const double *rates);
 
 typedef struct mpchol_mlp *mpchol_mlp_t;
 

@@ -1193,9 +1193,12 @@ extern "C" int mpchol_selector_features(mpchol_t h, double eps, float *feats)
 }
 
 // Greedy per-tile lowering under a measured backward-error budget.
-extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out)
+extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, double *berr_out, const double *rates)
 {
     if (!h || !labels || !(eps > 0)) return MPCHOL_EINVAL;
+    if (rates)
+        for (int q = 0; q < 4; ++q)
+            if (!(rates[q] > 0)) return MPCHOL_EINVAL;
     if (h->state < S_SOURCE) return MPCHOL_EORDER;
     HIPCHK(hipSetDevice(h->dev));
     const int nt = h->nt, w = h->o.band;
@@ -1240,9 +1243,12 @@ extern "C" int mpchol_selector_labels(mpchol_t h, double eps, uint8_t *labels, d
         }
     }
     // greedy: time weight of tile (I,J) = J updates of 2b^3 flops at the rate
-    // the update kernels reach on MI355X (TFLOP/s; the 16-bit and FP8 classes
-    // are bound by HBM, not by their MFMA peaks)
-    const double rate[4] = {58.0, 130.0, 600.0, 700.0};
+    // of each class's update kernel (TFLOP/s): the caller's, or those the
+    // kernels reach inside the factorization at N = 129,600 on MI355X (the
+    // 16-bit and FP8 updates are bound by their output traffic, not by their
+    // MFMA peaks)
+    const double rate_default[4] = {61.0, 168.0, 770.0, 850.0};
+    const double *rate = rates ? rates : rate_default;
     std::vector<uint8_t> cur((size_t)nt * nt, 0);
     double used = 0.0;
     struct Move {

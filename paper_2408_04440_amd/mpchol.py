@@ -98,7 +98,7 @@ def lib():
             "mpchol_last_error": (C.c_char_p, []),
             "mpchol_selector_set": (C.c_int, [vp, vp, i64]),
             "mpchol_selector_features": (C.c_int, [vp, d, vp]),
-            "mpchol_selector_labels": (C.c_int, [vp, d, vp, C.POINTER(d)]),
+            "mpchol_selector_labels": (C.c_int, [vp, d, vp, C.POINTER(d), vp]),
             "mpchol_mlp_create": (C.c_int, [C.POINTER(vp), i32, vp]),
             "mpchol_mlp_destroy": (C.c_int, [vp]),
             "mpchol_mlp_set_params": (C.c_int, [vp, vp, i64]),
@@ -380,11 +380,15 @@ def mpchol_selector_features(h, eps, nt):
     return f
 
 
-def mpchol_selector_labels(h, eps, nt):
+def mpchol_selector_labels(h, eps, nt, rates=None):
+    """(labels, measured backward error); rates: optional per-class update rates (4 values, TFLOP/s)."""
     lab = np.zeros((nt, nt), dtype=np.uint8, order="F")
     be = C.c_double(0.0)
-    _chk(lib().mpchol_selector_labels(h, float(eps), lab.ctypes.data_as(C.c_void_p), C.byref(be)),
-         "mpchol_selector_labels")
+    r = None if rates is None else np.ascontiguousarray(rates, dtype=np.float64)
+    if r is not None and r.size != 4:
+        raise ValueError("rates: 4 values (FP64, FP32, 16-bit, FP8)")
+    _chk(lib().mpchol_selector_labels(h, float(eps), lab.ctypes.data_as(C.c_void_p), C.byref(be),
+                                      None if r is None else r.ctypes.data_as(C.c_void_p)), "mpchol_selector_labels")
     return lab, be.value
 
 

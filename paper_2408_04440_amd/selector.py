@@ -31,10 +31,11 @@ def he_uniform_init(seed: int = 3) -> np.ndarray:
     return p.astype(np.float32)
 
 
-def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, device=0, label_eps=None):
+def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, device=0, label_eps=None, rates=None):
     """(features [m x 8], labels [m], verified backward error) of the off-band
     tiles of one synthetic matrix; labels for the budget of `label_eps`
-    (default eps), features relative to `eps`."""
+    (default eps), features relative to `eps`; rates: the per-class update
+    rates the greedy lowering weighs time with (default: the library's)."""
     import synth
 
     sigma, x = synth.workload(L, seed)
@@ -43,7 +44,7 @@ def label_matrix(L, tile, rho, seed, eps, nugget=1e-8, band=1, lo16=M.LO16_F16, 
     h = M.mpchol_create(n, tile, device=device, lo16=lo16, band=band)
     try:
         M.mpchol_set_generator(h, sigma, x, rho, nugget)
-        labels, berr = M.mpchol_selector_labels(h, eps if label_eps is None else label_eps, nt)
+        labels, berr = M.mpchol_selector_labels(h, eps if label_eps is None else label_eps, nt, rates)
         feats = M.mpchol_selector_features(h, eps, nt)
     finally:
         M.mpchol_destroy(h)
