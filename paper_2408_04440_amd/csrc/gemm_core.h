@@ -142,6 +142,96 @@ __device__ inline void cm_block(const T *__restrict__ A, int64_t lda, const T *_
     }
 }
 
+// cm_block with the global loads issued two K slices ahead (two register
+// sets, slice kt + 2 in flight while slice kt is multiplied and slice kt + 1
+// waits in registers), the same LDS stages and the same products in the same
+// order, so the results are bit-identical.  The number of slices (K / BK, or
+// twice that with A2/B2) must be even.
+template <typename T, int BM, int BN, int BK, int WM = 2, int WN = 2, bool SWAP = false>
+__device__ inline void cm_block_deep(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb, int K,
+                                     typename CM<T>::acc_t (&acc)[CMShape<T, BM, BN, BK, WM, WN>::MB]
+                                                                   [CMShape<T, BM, BN, BK, WM, WN>::NB],
+                                     T *smem, const T *__restrict__ A2 = nullptr, const T *__restrict__ B2 = nullptr)
+{
+    typedef CMShape<T, BM, BN, BK, WM, WN> S;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int gi = lane & 15, gg = lane >> 4;
+    T *As = smem;                       // [2][BK][LDM]
+    T *Bs = smem + 2 * BK * S::LDM;     // [2][BK][LDN]
+    u32x4 ra0[S::CA], rb0[S::CB], ra1[S::CA], rb1[S::CB];
+    const int nk1 = K / BK, nk = A2 ? 2 * nk1 : nk1;
+
+    auto gload = [&](int kt, u32x4(&ra)[S::CA], u32x4(&rb)[S::CB]) {
+        const T *a = A, *bp = B;
+        if (kt >= nk1) {
+            a = A2;
+            bp = B2;
+            kt -= nk1;
+        }
+#pragma unroll
+        for (int c = 0; c < S::CA; ++c) {
+            int ch = tid + S::NTH * c;
+            int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
+            if (ch < S::CHA) ra[c] = *(const u32x4 *)(a + (r + (kt * BK + col) * (int)lda));
+        }
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            int ch = tid + S::NTH * c;
+            int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
+            if (ch < S::CHB) rb[c] = *(const u32x4 *)(bp + (r + (kt * BK + col) * (int)ldb));
+        }
+    };
+    auto sstore = [&](int buf, const u32x4(&ra)[S::CA], const u32x4(&rb)[S::CB]) {
+#pragma unroll
+        for (int c = 0; c < S::CA; ++c) {
+            int ch = tid + S::NTH * c;
+            int col = ch / (BM / S::VEC), r = (ch % (BM / S::VEC)) * S::VEC;
+            if (ch < S::CHA) *(u32x4 *)(As + (buf * BK + col) * S::LDM + r) = ra[c];
+        }
+#pragma unroll
+        for (int c = 0; c < S::CB; ++c) {
+            int ch = tid + S::NTH * c;
+            int col = ch / (BN / S::VEC), r = (ch % (BN / S::VEC)) * S::VEC;
+            if (ch < S::CHB) *(u32x4 *)(Bs + (buf * BK + col) * S::LDN + r) = rb[c];
+        }
+    };
+    auto compute = [&](int cur) {
+        const T *as = As + cur * BK * S::LDM + wm * (BM / WM) + gi;
+        const T *bs = Bs + cur * BK * S::LDN + wn * (BN / WN) + gi;
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s) {
+            T fa[S::MB], fb[S::NB];
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m) fa[m] = as[(s * 4 + gg) * S::LDM + m * 16];
+#pragma unroll
+            for (int n = 0; n < S::NB; ++n) fb[n] = bs[(s * 4 + gg) * S::LDN + n * 16];
+#pragma unroll
+            for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                for (int n = 0; n < S::NB; ++n)
+                    acc[m][n] = SWAP ? CM<T>::mfma(fb[n], fa[m], acc[m][n]) : CM<T>::mfma(fa[m], fb[n], acc[m][n]);
+        }
+    };
+
+    gload(0, ra0, rb0);
+    gload(1, ra1, rb1);
+    sstore(0, ra0, rb0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+        // slice kt staged in LDS buffer 0, slice kt + 1 in the second register set
+        if (kt + 2 < nk) gload(kt + 2, ra0, rb0);
+        compute(0);
+        sstore(1, ra1, rb1);
+        __syncthreads();
+        // slice kt + 1 staged in buffer 1, slice kt + 2 in the first set
+        if (kt + 3 < nk) gload(kt + 3, ra1, rb1);
+        compute(1);
+        if (kt + 2 < nk) sstore(0, ra0, rb0);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- rm (FP16 / BF16 / FP8)
 enum { RM_F16 = 0, RM_BF16 = 1, RM_FP8 = 2 };
 
