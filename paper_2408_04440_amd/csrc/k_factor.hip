@@ -64,23 +64,24 @@ __global__ __launch_bounds__(64) void potrf_block_kernel(double *tile, int b, in
 }
 
 // ---------------------------------------------------------------- TRSM
-// X = W L^-T for strips of 64 rows (X L^T = W, L lower nL x nL, FP64).
-// Column blocks of 32: the block's right-hand side W - X_left L_row^T is
-// formed with FP64 MFMA from the already solved columns (operands staged
-// through LDS 32 columns at a time), then solved by forward substitution
-// against the 32 x 32 diagonal block, one row per lane in registers.
+// X = W L^-T for strips of 64 rows (X L^T = W, L lower nL x nL, FP64), four
+// waves per strip, each owning 16 rows.  Column blocks of 32: the block's
+// right-hand side W - X_left L_row^T is formed with FP64 MFMA from the
+// already solved columns -- each wave reads its own rows of X and the L rows
+// straight into registers, the next 48 columns of K in flight while the
+// current ones are multiplied, with no barrier inside the K loop -- then
+// solved by forward substitution against the 32 x 32 diagonal block, one row
+// per lane in registers.
 // mode 0: the panel of step k -- item I = k+1+blockIdx.y, W = tile (I,k) in
 //         its work precision (FP64, or FP32 for lower classes), X = p64[I];
 // mode 1: one FP64 strip set in place (W = X = xin, leading dimension ldin).
-constexpr int TPAD = 4;
-__global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, const double *L, int64_t ldl, int nL,
-                                                   double *xin, int64_t ldin, int mode)
+// nL is a multiple of 32.
+__global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, const double *__restrict__ L, int64_t ldl,
+                                                   int nL, double *xin, int64_t ldin, int mode)
 {
     __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
-    __shared__ double xs[32][64 + TPAD];  // X chunk: xs[k][row]
-    __shared__ double ls[32][32 + TPAD];  // L chunk: ls[k][c] = L(cb + c, k0 + k)
-    __shared__ double ts[32][64 + 1];     // right-hand side / solution: ts[c][row]
-    __shared__ double lb[32][33];         // diagonal block: lb[c][r] = L(cb + r, cb + c)
+    __shared__ double ts[32][64 + 1];  // right-hand side / solution: ts[c][row]
+    __shared__ double lb[32][33];      // diagonal block: lb[cc][c] = L(cb + c, cb + cc)
     const void *W;
     bool wf32 = false;
     int64_t ldw, ldx;
@@ -105,71 +106,81 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
 
     for (int cb = 0; cb < nL; cb += 32) {
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < cb; k0 += 32) {
-            // stage X(rows, k0..k0+31) and L(cb..cb+31, k0..k0+31)
-            {
-                int e = tid;  // 4 x 16-byte chunks of X per thread: 32 cols x 32 chunks
+        // MFMA k-step kk (4 columns of K): a = X(row0 + 16 wave + gi, kk + gg),
+        // b_n = L(cb + 16 n + gi, kk + gg); chunks of four k-steps
+        const double *xa = Xs + wave * 16 + gi + (int64_t)gg * ldx;
+        const double *lp = L + (cb + gi) + (int64_t)gg * ldl;
+        double a0[4], b0[4][2], a1[4], b1[4][2], a2[4], b2[4][2], a3[4], b3[4][2];
+        // offsets within one tile (below b * b), kept in 32 bits
+        const int ldx32 = (int)ldx, ldl32 = (int)ldl;
+        auto load = [&](int kc, double(&a)[4], double(&bv)[4][2]) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    int ch = e + 256 * q, kk = ch >> 5, r = (ch & 31) * 2;
-                    const double *src = Xs + r + (int64_t)(k0 + kk) * ldx;
-                    xs[kk][r] = src[0];
-                    xs[kk][r + 1] = src[1];
-                }
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    int ch = e + 256 * q, kk = ch >> 4, c = (ch & 15) * 2;
-                    const double *src = L + (cb + c) + (int64_t)(k0 + kk) * ldl;
-                    ls[kk][c] = src[0];
-                    ls[kk][c + 1] = src[1];
-                }
+            for (int s = 0; s < 4; ++s) {
+                const int kk = kc * 16 + 4 * s;
+                a[s] = xa[kk * ldx32];
+                bv[s][0] = lp[kk * ldl32];
+                bv[s][1] = lp[16 + kk * ldl32];
             }
-            __syncthreads();
+        };
+        auto mma = [&](const double(&a)[4], const double(&bv)[4][2]) {
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                double av = xs[s * 4 + gg][wave * 16 + gi];
-                double b0 = ls[s * 4 + gg][gi];
-                double b1 = ls[s * 4 + gg][16 + gi];
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc1, 0, 0, 0);
+            for (int s = 0; s < 4; ++s) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bv[s][0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bv[s][1], acc1, 0, 0, 0);
             }
-            __syncthreads();
+        };
+        // three chunks in flight (a chunk is 512 cycles of MFMA work, well
+        // short of a load's latency); nc is even
+        const int nc = cb / 16;
+        if (nc > 0) {
+            load(0, a0, b0);
+            load(1, a1, b1);
+            if (nc > 2) load(2, a2, b2);
+            for (int kc = 0; kc < nc; kc += 4) {
+                if (kc + 3 < nc) load(kc + 3, a3, b3);
+                mma(a0, b0);
+                if (kc + 4 < nc) load(kc + 4, a0, b0);
+                mma(a1, b1);
+                if (kc + 2 >= nc) break;
+                if (kc + 5 < nc) load(kc + 5, a1, b1);
+                mma(a2, b2);
+                if (kc + 6 < nc) load(kc + 6, a2, b2);
+                mma(a3, b3);
+            }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            int r = wave * 16 + acc_row<double>(gg, v);
-            int64_t o0 = (int64_t)(row0 + r) + (int64_t)(cb + gi) * ldw;
-            int64_t o1 = o0 + 16 * ldw;
-            double w0 = wf32 ? (double)((const float *)W)[o0] : ((const double *)W)[o0];
-            double w1 = wf32 ? (double)((const float *)W)[o1] : ((const double *)W)[o1];
+            const int r = wave * 16 + acc_row<double>(gg, v);
+            const int64_t o0 = (int64_t)(row0 + r) + (int64_t)(cb + gi) * ldw;
+            const int64_t o1 = o0 + 16 * ldw;
+            const double w0 = wf32 ? (double)((const float *)W)[o0] : ((const double *)W)[o0];
+            const double w1 = wf32 ? (double)((const float *)W)[o1] : ((const double *)W)[o1];
             ts[gi][r] = w0 - acc0[v];
             ts[16 + gi][r] = w1 - acc1[v];
         }
         for (int e = tid; e < 32 * 32; e += 256) {
-            int r = e & 31, c = e >> 5;
-            lb[c][r] = L[(cb + r) + (int64_t)(cb + c) * ldl];
+            const int c = e & 31, cc = e >> 5;
+            lb[cc][c] = L[(cb + c) + (int64_t)(cb + cc) * ldl];
         }
         __syncthreads();
         if (wave == 0) {
             double t[32];
 #pragma unroll
             for (int c = 0; c < 32; ++c) t[c] = ts[c][lane];
+            // column by column: once x_c is final it is divided out and
+            // subtracted from every later column of the row -- each x_j still
+            // receives its terms in increasing c, then its division, but the
+            // updates of different j are independent of each other
 #pragma unroll
             for (int c = 0; c < 32; ++c) {
-                double xv = t[c];
+                t[c] = t[c] / lb[c][c];
 #pragma unroll
-                for (int cc = 0; cc < c; ++cc) xv -= t[cc] * lb[cc][c];
-                t[c] = xv / lb[c][c];
+                for (int j = c + 1; j < 32; ++j) t[j] -= t[c] * lb[c][j];
             }
 #pragma unroll
-            for (int c = 0; c < 32; ++c) ts[c][lane] = t[c];
+            for (int c = 0; c < 32; ++c) Xs[lane + (int64_t)(cb + c) * ldx] = t[c];
         }
-        __syncthreads();
-        for (int e = tid; e < 64 * 32; e += 256) {
-            int r = e & 63, c = e >> 6;
-            Xs[r + (int64_t)(cb + c) * ldx] = ts[c][r];
-        }
-        __syncthreads();
+        __syncthreads();  // the solved columns are read back by the next column block
     }
 }
 
