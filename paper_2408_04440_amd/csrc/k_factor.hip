@@ -74,6 +74,8 @@ __global__ __launch_bounds__(64) void potrf_block_kernel(double *tile, int b, in
 // per lane in registers.
 // mode 0: the panel of step k -- item I = k+1+blockIdx.y, W = tile (I,k) in
 //         its work precision (FP64, or FP32 for lower classes), X = p64[I];
+//         the strip's largest |X| is folded into pmax[I] (atomic max of the
+//         FP64 bits, which order like the values; the caller zeroes pmax);
 // mode 1: one FP64 strip set in place (W = X = xin, leading dimension ldin).
 // nL is a multiple of 32.
 __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, const double *__restrict__ L, int64_t ldl,
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gi = lane & 15, gg = lane >> 4;
     double *Xs = X + row0;
+    double xmax = 0.0;  // wave 0: largest |X| written
 
     for (int cb = 0; cb < nL; cb += 32) {
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
@@ -178,9 +181,17 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
                 for (int j = c + 1; j < 32; ++j) t[j] -= t[c] * lb[c][j];
             }
 #pragma unroll
-            for (int c = 0; c < 32; ++c) Xs[lane + (int64_t)(cb + c) * ldx] = t[c];
+            for (int c = 0; c < 32; ++c) {
+                Xs[lane + (int64_t)(cb + c) * ldx] = t[c];
+                xmax = fmax(xmax, fabs(t[c]));
+            }
         }
         __syncthreads();  // the solved columns are read back by the next column block
+    }
+    if (mode == 0 && wave == 0) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) xmax = fmax(xmax, __shfl_xor(xmax, off));
+        if (lane == 0) atomicMax(P.pmax + k + 1 + blockIdx.y, (unsigned long long)__double_as_longlong(xmax));
     }
 }
 

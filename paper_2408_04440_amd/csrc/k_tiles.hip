@@ -88,27 +88,6 @@ __global__ __launch_bounds__(256) void copy_matrix_kernel(Tiles T, const double 
     }
 }
 
-// max |X| of each TRSM output tile of step k (FP64 bit patterns of
-// non-negative values order like unsigned integers).
-__global__ __launch_bounds__(256) void panel_max_kernel(Tiles T, Panel P, int k)
-{
-    __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
-    __shared__ double sm[256];
-    const int I = k + 1 + blockIdx.y;
-    const int64_t bb = (int64_t)T.b * T.b;
-    const int64_t chunk = bb / gridDim.x;
-    const double *x = P.p64 + (int64_t)I * bb + chunk * blockIdx.x;
-    double m = 0.0;
-    for (int64_t e = threadIdx.x; e < chunk; e += 256) m = fmax(m, fabs(x[e]));
-    sm[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(P.pmax + I, (unsigned long long)__double_as_longlong(sm[0]));
-}
-
 // Sender-side conversion of step k (one 64 x 64 sub-tile per block).
 // The TRSM output X (FP64, in p64[I]) becomes the stored value S of tile
 // (I,k) in its class -- FP64: X; FP32: (float)X; 16-bit/FP8: the scaled,
@@ -254,13 +233,6 @@ void launch_copy_matrix(const Tiles &T, const double *A, int64_t lda, double *or
 {
     int64_t bb = (int64_t)T.b * T.b;
     copy_matrix_kernel<<<dim3((unsigned)((bb + 2047) / 2048), (unsigned)ntiles(T)), 256, 0, st>>>(T, A, lda, orig);
-}
-
-void launch_panel_max(const Tiles &T, const Panel &P, int k, hipStream_t st)
-{
-    int np = T.nt - k - 1;
-    if (np <= 0) return;
-    panel_max_kernel<<<dim3(16, np), 256, 0, st>>>(T, P, k);
 }
 
 void launch_convert(const Tiles &T, const Panel &P, int k, const uint8_t *qmask, hipStream_t st)

@@ -46,7 +46,6 @@ struct Panel {
 void launch_norms(const Tiles &T, const Source &S, double *fro2, double *amax, hipStream_t st);
 void launch_load(const Tiles &T, const Source &S, hipStream_t st);
 void launch_copy_matrix(const Tiles &T, const double *A, int64_t lda, double *orig, hipStream_t st);
-void launch_panel_max(const Tiles &T, const Panel &P, int k, hipStream_t st);
 void launch_convert(const Tiles &T, const Panel &P, int k, const uint8_t *qmask, hipStream_t st);
 void launch_logdet(const Tiles &T, double *out, hipStream_t st);
 void launch_get_factor(const Tiles &T, double *L, int64_t ldl, hipStream_t st);

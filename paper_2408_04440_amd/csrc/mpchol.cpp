@@ -713,12 +713,12 @@ extern "C" int mpchol_precision_map(mpchol_t h, int32_t rule, double eps, const 
 }
 
 // Panel work of step k on stream st: TRSM of the tiles below the diagonal
-// into the FP64 panel, max |X| per tile, and the sender-side conversion.
+// into the FP64 panel (which also takes max |X| per tile), and the
+// sender-side conversion.
 static int panel_step(mpchol_handle *h, const Tiles &T, const Panel &P, int k, hipStream_t st)
 {
-    launch_trsm_panel(T, P, k, st);
     HIPCHK(hipMemsetAsync(P.pmax, 0, (size_t)h->nt * 8, st));
-    launch_panel_max(T, P, k, st);
+    launch_trsm_panel(T, P, k, st);
     launch_convert(T, P, k, h->d_qmask + (size_t)k * h->nt, st);
     if (h->d_ozc) launch_ozaki_convert(T, P, k, h->d_qmask + (size_t)k * h->nt, h->d_ozc, st);
     return MPCHOL_OK;

@@ -110,6 +110,57 @@ def test_sample_z_matches_oracle_product(orc, rule, eps):
     assert rel <= 1e-5
 
 
+@pytest.mark.parametrize("n,kind", [(4096, "integer"), (3600, "integer"), (3600, "covariance")])
+def test_sample_z_tile1024_mixed(orc, n, kind):
+    """Y = L Z at the benchmark's tile size, 1024, with FP32, FP16 and FP8
+    tiles (the second and third cases have a 528-row last tile): against the
+    oracle's FP64 product of the GPU's own factor (its represented values) to
+    1e-5, as a whole and row tile by row tile.  "integer": A = L0 L0^T with a
+    user map cycling the three lower classes below the diagonal (the factor
+    is L0 exactly); "covariance": the band-limit-60 covariance under the norm
+    rule at eps = 1e-5."""
+    torch = torch_cuda()
+    tile, nd = 1024, 64
+    nt = (n + tile - 1) // tile
+    mod = M()
+    h = mod.mpchol_create(n, tile)
+    try:
+        if kind == "integer":
+            L0 = synth.int_lower(n, 29)
+            mod.mpchol_set_matrix(h, L0 @ L0.T)
+            um = np.zeros((nt, nt), np.uint8)
+            for J in range(nt):
+                for I in range(J + 1, nt):
+                    um[I, J] = 1 + (I + J) % 3
+            mp = mod.mpchol_precision_map(h, mod.RULE_USER, 1e-9, np.asfortranarray(um))
+        else:
+            L = int(round(np.sqrt(n)))
+            sigma, x = synth.workload(L)
+            mod.mpchol_set_generator(h, sigma, x, 5.0, 1e-8)
+            mp = mod.mpchol_precision_map(h, mod.RULE_NORM, 1e-5)
+        assert mod.mpchol_factor(h) == 0
+        Lg = factor_dense(h, n)
+        Z = synth.draws(n, nd, 31)
+        Zt = torch.tensor(np.ascontiguousarray(Z.T), device="cuda")
+        Yt = torch.zeros((nd, n), dtype=torch.float32, device="cuda")
+        mod.mpchol_sample_z(h, Zt.T, Yt.T, n)
+        torch.cuda.synchronize()
+        Y = Yt.T.cpu().numpy().astype(np.float64)
+    finally:
+        mod.mpchol_destroy(h)
+    hist = np.bincount(mp[np.tril_indices(nt, -1)], minlength=4)
+    if kind == "integer":
+        assert np.array_equal(Lg, L0) and np.all(hist[1:] > 0)
+    else:
+        assert np.count_nonzero(hist) >= 2
+    Yg = orc.lower_matmul(Lg, Z.astype(np.float64))
+    rel = np.linalg.norm(Y - Yg) / np.linalg.norm(Yg)
+    worst = max(np.linalg.norm(Y[r:r + tile] - Yg[r:r + tile]) / np.linalg.norm(Yg[r:r + tile])
+                for r in range(0, n, tile))
+    log(f"  sample_z tile 1024 n={n} {kind}: hist={hist} rel={rel:.2e} worst row tile {worst:.2e}")
+    assert rel <= 1e-5 and worst <= 1e-5
+
+
 def test_sample_is_philox_then_product(orc):
     """mpchol_sample(seed) equals mpchol_sample_z on the draws of the same seed,
     and the draws have the covariance of Sigma (per-coordinate variances)."""

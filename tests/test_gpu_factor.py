@@ -55,7 +55,8 @@ def test_fp64_parity_small(orc, L, tile, rho):
 
 @pytest.mark.parametrize("n,tile,lo16,kind", [
     (1024, 128, 0, "fp64"), (1024, 128, 0, "mixed"), (1024, 128, 1, "mixed"),
-    (1000, 128, 0, "mixed"), (1152, 256, 0, "mixed"), (640, 128, 1, "all8"), (777, 128, 0, "all16")])
+    (1000, 128, 0, "mixed"), (1152, 256, 0, "mixed"), (640, 128, 1, "all8"), (777, 128, 0, "all16"),
+    (4096, 1024, 0, "mixed"), (3600, 1024, 1, "mixed")])
 def test_integer_factor_bit_exact(n, tile, lo16, kind):
     """A = L0 L0^T with small integers: every class computes L0 exactly, so the
     GPU factor must equal L0 bit for bit (covers MFMA layouts, scaling, FP8
