@@ -108,6 +108,22 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
     double xmax = 0.0;  // wave 0: largest |X| written
 
     for (int cb = 0; cb < nL; cb += 32) {
+        // this column block's right-hand side and diagonal block, read before
+        // the K loop so that their latency overlaps its first loads
+        double wv[4][2], lv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = wave * 16 + acc_row<double>(gg, v);
+            const int64_t o0 = (int64_t)(row0 + r) + (int64_t)(cb + gi) * ldw;
+            const int64_t o1 = o0 + 16 * ldw;
+            wv[v][0] = wf32 ? (double)((const float *)W)[o0] : ((const double *)W)[o0];
+            wv[v][1] = wf32 ? (double)((const float *)W)[o1] : ((const double *)W)[o1];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q, c = e & 31, cc = e >> 5;
+            lv[q] = L[(cb + c) + (int64_t)(cb + cc) * ldl];
+        }
         double4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
         // MFMA k-step kk (4 columns of K): a = X(row0 + 16 wave + gi, kk + gg),
         // b_n = L(cb + 16 n + gi, kk + gg); chunks of four k-steps
@@ -154,16 +170,13 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = wave * 16 + acc_row<double>(gg, v);
-            const int64_t o0 = (int64_t)(row0 + r) + (int64_t)(cb + gi) * ldw;
-            const int64_t o1 = o0 + 16 * ldw;
-            const double w0 = wf32 ? (double)((const float *)W)[o0] : ((const double *)W)[o0];
-            const double w1 = wf32 ? (double)((const float *)W)[o1] : ((const double *)W)[o1];
-            ts[gi][r] = w0 - acc0[v];
-            ts[16 + gi][r] = w1 - acc1[v];
+            ts[gi][r] = wv[v][0] - acc0[v];
+            ts[16 + gi][r] = wv[v][1] - acc1[v];
         }
-        for (int e = tid; e < 32 * 32; e += 256) {
-            const int c = e & 31, cc = e >> 5;
-            lb[cc][c] = L[(cb + c) + (int64_t)(cb + cc) * ldl];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q, c = e & 31, cc = e >> 5;
+            lb[cc][c] = lv[q];
         }
         __syncthreads();
         if (wave == 0) {
