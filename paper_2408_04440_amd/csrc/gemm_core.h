@@ -339,6 +339,10 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
         if (kt + 1 < nk) gload(kt + 1);
         const uint8_t *as = As + (cur * BM + wm * (BM / WM) + gi) * S::LDB;
         const uint8_t *bs = Bs + (cur * BN + wn * (BN / WN) + gi) * S::LDB;
+        // raised issue priority while multiplying, so that a wave whose
+        // operands are in LDS goes ahead of waves still loading (measured
+        // +0.4% on the mixed factorization)
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int s = 0; s < BK / RM<KIND>::KSTEP; ++s) {
             constexpr int KS = RM<KIND>::KSTEP;  // K per instruction; KS / 4 per lane
@@ -353,6 +357,7 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
 #pragma unroll
                 for (int n = 0; n < S::NB; ++n) acc[m][n] = RM<KIND>::mfma(fa[m], fb[n], acc[m][n]);
         }
+        __builtin_amdgcn_s_setprio(0);
         if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
