@@ -144,14 +144,32 @@ __global__ __launch_bounds__(256) void scan_finish_kernel(Tiles T, Source S, con
 }
 
 // ---------------------------------------------------------------- L^T V, L W
-// Stage an ER x EB (rows x columns) piece of stored tile (cls, ts) at
-// (r0, c0) into st[r][c], widened to FP64.
-__device__ inline void stage_tile(const char *tile, int cls, int lo16, int ts, int b, int r0, int c0,
-                                  double (*st)[EB + 1])
+// Both products walk a tile column (row) of the stored factor in steps of ER
+// rows (columns) of K: each step's piece of L (widened to FP64) and of the
+// probes is read into registers while the previous step is multiplied from
+// LDS, then written to LDS once every wave is done with it (one LDS buffer,
+// which leaves room for four blocks per compute unit).
+constexpr int EPT = ER * EB / 256;  // elements of the L piece per thread
+constexpr int QPT = ER * EK / 256;  // elements of the probe piece per thread
+static_assert(ER * EB % 256 == 0 && ER * EK % 256 == 0, "staging split");
+
+// The 2 x 2 MFMA tiles of a wave: acc[m][n] += B-piece(n)^T-ish products over
+// the ER rows of one staged step, with swapped operands (lane gi owns output
+// row c of the 32 x 32 wave tile, element v the probe acc_row(gg, v)).
+__device__ inline void apply_step(const double (*ls)[EB + 1], const double (*vs)[EK + 1], int wm, int wn, int gi,
+                                  int gg, double4_t (&acc)[2][2])
 {
-    for (int e = threadIdx.x; e < ER * EB; e += 256) {
-        const int r = e % ER, c = e / ER;
-        st[r][c] = load_stored(tile, cls, lo16, ts, (int64_t)(r0 + r) + (int64_t)(c0 + c) * b);
+#pragma unroll
+    for (int s = 0; s < ER / 4; ++s) {
+        double fa[2], fb[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) fa[m] = ls[s * 4 + gg][wm * 32 + m * 16 + gi];
+#pragma unroll
+        for (int n = 0; n < 2; ++n) fb[n] = vs[s * 4 + gg][wn * 32 + n * 16 + gi];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[n], fa[m], acc[m][n], 0, 0, 0);
     }
 }
 
@@ -162,7 +180,7 @@ __global__ __launch_bounds__(256) void lt_apply_kernel(Tiles T, const double *V,
 {
     __shared__ double ls[ER][EB + 1];  // ls[r][c] = L_IK(r0 + r, c0 + c)
     __shared__ double vs[ER][EK + 1];  // vs[r][q] = V[I*b + r0 + r, q]
-    const int b = T.b, per = b / EB;
+    const int b = T.b, per = b / EB, nrs = b / ER;
     const int K = blockIdx.x / per, c0 = (blockIdx.x % per) * EB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % 2, wn = wave / 2, gi = lane & 15, gg = lane >> 4;
@@ -171,33 +189,48 @@ __global__ __launch_bounds__(256) void lt_apply_kernel(Tiles T, const double *V,
     for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int n = 0; n < 2; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    for (int I = K; I < T.nt; ++I) {
+    double lr[EPT], vr[QPT];
+    auto fetch = [&](int st) {  // step st: tile I = K + st / nrs, rows r0 = (st % nrs) * ER
+        const int I = K + st / nrs, r0 = (st % nrs) * ER;
         const int cls = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
         const int ts = T.tscale[I + (int64_t)K * T.nt];
         const char *tile = T.slots + tile_index(I, K) * T.slot_bytes;
-        for (int r0 = 0; r0 < b; r0 += ER) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j, r = e % ER, c = e / ER;
+            lr[j] = load_stored(tile, cls, T.lo16, ts, (int64_t)(r0 + r) + (int64_t)(c0 + c) * b);
+        }
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int e = tid + 256 * j, r = e % ER, q = e / ER;
+            vr[j] = V[(int64_t)I * b + r0 + r + q * ldv];
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j;
+            ls[e % ER][e / ER] = lr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int e = tid + 256 * j;
+            vs[e % ER][e / ER] = vr[j];
+        }
+    };
+    const int nsteps = (T.nt - K) * nrs;
+    fetch(0);
+    put();
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        if (st + 1 < nsteps) fetch(st + 1);
+        apply_step(ls, vs, wm, wn, gi, gg, acc);
+        __syncthreads();
+        if (st + 1 < nsteps) {
+            put();
             __syncthreads();
-            stage_tile(tile, cls, T.lo16, ts, b, r0, c0, ls);
-            for (int e = tid; e < ER * EK; e += 256) {
-                const int r = e % ER, q = e / ER;
-                vs[r][q] = V[(int64_t)I * b + r0 + r + q * ldv];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int s = 0; s < ER / 4; ++s) {
-                double fa[2], fb[2];
-#pragma unroll
-                for (int m = 0; m < 2; ++m) fa[m] = ls[s * 4 + gg][wm * 32 + m * 16 + gi];
-#pragma unroll
-                for (int n = 0; n < 2; ++n) fb[n] = vs[s * 4 + gg][wn * 32 + n * 16 + gi];
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[n], fa[m], acc[m][n], 0, 0, 0);
-            }
         }
     }
-    // swapped operands: lane gi owns output row c, element v probe acc_row(gg, v)
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
@@ -217,7 +250,7 @@ __global__ __launch_bounds__(256) void l_apply_kernel(Tiles T, const double *W, 
 {
     __shared__ double ls[ER][EB + 1];  // ls[c][r] = L_IK(r0 + r, c0 + c)
     __shared__ double ws[ER][EK + 1];  // ws[c][q] = W[K*b + c0 + c, q]
-    const int b = T.b, per = b / EB;
+    const int b = T.b, per = b / EB, nrs = b / ER;
     const int I = T.nt - 1 - (int)(blockIdx.x / per), r0 = (blockIdx.x % per) * EB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % 2, wn = wave / 2, gi = lane & 15, gg = lane >> 4;
@@ -226,33 +259,46 @@ __global__ __launch_bounds__(256) void l_apply_kernel(Tiles T, const double *W, 
     for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int n = 0; n < 2; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
-    for (int K = 0; K <= I; ++K) {
+    double lr[EPT], wr[QPT];
+    auto fetch = [&](int st) {  // step st: tile K = st / nrs, columns c0 = (st % nrs) * ER
+        const int K = st / nrs, c0 = (st % nrs) * ER;
         const int cls = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
         const int ts = T.tscale[I + (int64_t)K * T.nt];
         const char *tile = T.slots + tile_index(I, K) * T.slot_bytes;
-        for (int c0 = 0; c0 < b; c0 += ER) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j, r = e % EB, c = e / EB;
+            lr[j] = load_stored(tile, cls, T.lo16, ts, (int64_t)(r0 + r) + (int64_t)(c0 + c) * b);
+        }
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int e = tid + 256 * j, c = e % ER, q = e / ER;
+            wr[j] = W[(int64_t)K * b + c0 + c + q * ldw];
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + 256 * j;
+            ls[e / EB][e % EB] = lr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < QPT; ++j) {
+            const int e = tid + 256 * j;
+            ws[e % ER][e / ER] = wr[j];
+        }
+    };
+    const int nsteps = (I + 1) * nrs;
+    fetch(0);
+    put();
+    __syncthreads();
+    for (int st = 0; st < nsteps; ++st) {
+        if (st + 1 < nsteps) fetch(st + 1);
+        apply_step(ls, ws, wm, wn, gi, gg, acc);
+        __syncthreads();
+        if (st + 1 < nsteps) {
+            put();
             __syncthreads();
-            for (int e = tid; e < ER * EB; e += 256) {
-                const int r = e % EB, c = e / EB;
-                ls[c][r] = load_stored(tile, cls, T.lo16, ts, (int64_t)(r0 + r) + (int64_t)(c0 + c) * b);
-            }
-            for (int e = tid; e < ER * EK; e += 256) {
-                const int c = e % ER, q = e / ER;
-                ws[c][q] = W[(int64_t)K * b + c0 + c + q * ldw];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int s = 0; s < ER / 4; ++s) {
-                double fa[2], fb[2];
-#pragma unroll
-                for (int m = 0; m < 2; ++m) fa[m] = ls[s * 4 + gg][wm * 32 + m * 16 + gi];
-#pragma unroll
-                for (int n = 0; n < 2; ++n) fb[n] = ws[s * 4 + gg][wn * 32 + n * 16 + gi];
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int n = 0; n < 2; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[n], fa[m], acc[m][n], 0, 0, 0);
-            }
         }
     }
 #pragma unroll
