@@ -318,6 +318,14 @@ int mpchol_mlp_destroy(mpchol_mlp_t m);
 /* host params in/out (nparam floats); set also zeroes the Adam moments */
 int mpchol_mlp_set_params(mpchol_mlp_t m, const float *params, int64_t nparam);
 int mpchol_mlp_get_params(mpchol_mlp_t m, float *params, int64_t nparam);
+/* The whole training state, for checkpoints that resume bit for bit: host
+ * params, Adam's first and second moments m1, m2 (nparam floats each, caller
+ * owned) and the number of Adam steps taken (the bias corrections use it).
+ * set_state: EINVAL for null pointers, nparam != MPCHOL_MLP_NPARAM, step < 0
+ * or a second moment that is negative or NaN.  Both synchronize. */
+int mpchol_mlp_get_state(mpchol_mlp_t m, float *params, float *m1, float *m2, int32_t *step, int64_t nparam);
+int mpchol_mlp_set_state(mpchol_mlp_t m, const float *params, const float *m1, const float *m2, int32_t step,
+                         int64_t nparam);
 /* loss and gradient (device grad, nparam floats) of the batch: device X
  * (nb x 8 row-major), device y (nb int32 labels), host class weights cw[4];
  * per-sample loss w_y (-log p_y) + alpha sum_{c>y} p_c, mean over the batch. */

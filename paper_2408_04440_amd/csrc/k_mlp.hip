@@ -370,6 +370,32 @@ int mpchol_mlp_get_params(mpchol_mlp_t t, float *params, int64_t np)
     return hipStreamSynchronize(t->st) == hipSuccess ? MPCHOL_OK : MPCHOL_EHIP;
 }
 
+int mpchol_mlp_get_state(mpchol_mlp_t t, float *params, float *m1, float *m2, int32_t *step, int64_t np)
+{
+    if (!t || !params || !m1 || !m2 || !step || np != NP) return MPCHOL_EINVAL;
+    if (hipSetDevice(t->dev) != hipSuccess) return MPCHOL_EHIP;
+    if (hipMemcpyAsync(params, t->P, NP * 4, hipMemcpyDeviceToHost, t->st) != hipSuccess) return MPCHOL_EHIP;
+    if (hipMemcpyAsync(m1, t->m, NP * 4, hipMemcpyDeviceToHost, t->st) != hipSuccess) return MPCHOL_EHIP;
+    if (hipMemcpyAsync(m2, t->v, NP * 4, hipMemcpyDeviceToHost, t->st) != hipSuccess) return MPCHOL_EHIP;
+    if (hipStreamSynchronize(t->st) != hipSuccess) return MPCHOL_EHIP;
+    *step = t->step;
+    return MPCHOL_OK;
+}
+
+int mpchol_mlp_set_state(mpchol_mlp_t t, const float *params, const float *m1, const float *m2, int32_t step,
+                         int64_t np)
+{
+    if (!t || !params || !m1 || !m2 || step < 0 || np != NP) return MPCHOL_EINVAL;
+    for (int64_t i = 0; i < NP; ++i)  // Adam's second moment is a running mean of squares
+        if (!(m2[i] >= 0.0f)) return MPCHOL_EINVAL;
+    if (hipSetDevice(t->dev) != hipSuccess) return MPCHOL_EHIP;
+    if (hipMemcpyAsync(t->P, params, NP * 4, hipMemcpyHostToDevice, t->st) != hipSuccess) return MPCHOL_EHIP;
+    if (hipMemcpyAsync(t->m, m1, NP * 4, hipMemcpyHostToDevice, t->st) != hipSuccess) return MPCHOL_EHIP;
+    if (hipMemcpyAsync(t->v, m2, NP * 4, hipMemcpyHostToDevice, t->st) != hipSuccess) return MPCHOL_EHIP;
+    t->step = step;
+    return hipStreamSynchronize(t->st) == hipSuccess ? MPCHOL_OK : MPCHOL_EHIP;
+}
+
 int mpchol_mlp_grad(mpchol_mlp_t t, const float *X, const int32_t *y, int64_t nb, const float *cw, float alpha,
                     float *grad, float *loss)
 {

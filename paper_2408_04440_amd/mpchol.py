@@ -103,6 +103,8 @@ def lib():
             "mpchol_mlp_destroy": (C.c_int, [vp]),
             "mpchol_mlp_set_params": (C.c_int, [vp, vp, i64]),
             "mpchol_mlp_get_params": (C.c_int, [vp, vp, i64]),
+            "mpchol_mlp_get_state": (C.c_int, [vp, vp, vp, vp, C.POINTER(i32), i64]),
+            "mpchol_mlp_set_state": (C.c_int, [vp, vp, vp, vp, i32, i64]),
             "mpchol_mlp_grad": (C.c_int, [vp, vp, vp, i64, vp, C.c_float, vp, C.POINTER(C.c_float)]),
             "mpchol_mlp_train_step": (C.c_int, [vp, vp, vp, i64, vp, C.c_float, C.c_float, C.POINTER(C.c_float)]),
             "mpchol_mlp_predict": (C.c_int, [vp, vp, i64, vp, vp]),
@@ -411,6 +413,23 @@ def mpchol_mlp_get_params(m):
     p = np.zeros(MLP_NPARAM, dtype=np.float32)
     _chk(lib().mpchol_mlp_get_params(m, p.ctypes.data_as(C.c_void_p), p.size), "mpchol_mlp_get_params")
     return p
+
+
+def mpchol_mlp_get_state(m):
+    """(params, m1, m2, step): the trainer's parameters, Adam moments and step count."""
+    p, m1, m2 = (np.zeros(MLP_NPARAM, dtype=np.float32) for _ in range(3))
+    st = C.c_int32(0)
+    _chk(lib().mpchol_mlp_get_state(m, p.ctypes.data_as(C.c_void_p), m1.ctypes.data_as(C.c_void_p),
+                                    m2.ctypes.data_as(C.c_void_p), C.byref(st), MLP_NPARAM), "mpchol_mlp_get_state")
+    return p, m1, m2, int(st.value)
+
+
+def mpchol_mlp_set_state(m, params, m1, m2, step):
+    arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (params, m1, m2)]
+    if any(a.size != MLP_NPARAM for a in arrs):
+        raise ValueError(f"mpchol_mlp_set_state: params and moments need {MLP_NPARAM} values each")
+    _chk(lib().mpchol_mlp_set_state(m, *(a.ctypes.data_as(C.c_void_p) for a in arrs), int(step), MLP_NPARAM),
+         "mpchol_mlp_set_state")
 
 
 def _cw(cw):

@@ -64,13 +64,21 @@ def class_weights(y) -> np.ndarray:
     return w
 
 
-def train(X, y, steps=600, lr=3e-3, alpha=2.0, seed=3, device=0, log_every=0):
-    """Full-batch Adam on the GPU kernels; returns (params, losses)."""
+def train(X, y, steps=600, lr=3e-3, alpha=2.0, seed=3, device=0, log_every=0, state=None, return_state=False):
+    """Full-batch Adam on the GPU kernels; returns (params, losses), or with
+    return_state (params, losses, state).  state = (params, m1, m2, step), the
+    trainer's parameters, Adam moments and step count: passed back in, it
+    continues the same run bit for bit (the bias corrections use the step)."""
     import torch
 
     m = M.mpchol_mlp_create(device)
     try:
-        M.mpchol_mlp_set_params(m, he_uniform_init(seed))
+        if state is None:
+            M.mpchol_mlp_set_params(m, he_uniform_init(seed))
+            s0 = 0
+        else:
+            M.mpchol_mlp_set_state(m, *state)
+            s0 = int(state[3])
         Xt = torch.tensor(np.ascontiguousarray(X, dtype=np.float32), device=f"cuda:{device}")
         yt = torch.tensor(np.ascontiguousarray(y, dtype=np.int32), device=f"cuda:{device}")
         cw = class_weights(y)
@@ -79,11 +87,11 @@ def train(X, y, steps=600, lr=3e-3, alpha=2.0, seed=3, device=0, log_every=0):
             want = log_every and (s % log_every == 0 or s == steps - 1)
             l = M.mpchol_mlp_train_step(m, Xt, yt, cw, alpha, lr, want_loss=bool(want))
             if want:
-                losses.append((s, l))
-        params = M.mpchol_mlp_get_params(m)
+                losses.append((s0 + s, l))
+        st = M.mpchol_mlp_get_state(m)
     finally:
         M.mpchol_mlp_destroy(m)
-    return params, losses
+    return (st[0], losses, st) if return_state else (st[0], losses)
 
 
 def predict(params, X, device=0):
@@ -101,9 +109,27 @@ def predict(params, X, device=0):
         M.mpchol_mlp_destroy(m)
 
 
-def save(params, path=WEIGHTS, meta=None):
+def save(params, path=WEIGHTS, meta=None, state=None):
+    """Weights (and, with state = (params, m1, m2, step) from train, the Adam
+    moments and step, for a checkpoint that resumes training) as JSON; float32
+    values round-trip exactly."""
+    d = {"nparam": int(M.MLP_NPARAM), "params": [float(v) for v in params], "meta": meta or {}}
+    if state is not None:
+        d["adam"] = {"m1": [float(v) for v in state[1]], "m2": [float(v) for v in state[2]], "step": int(state[3])}
     with open(path, "w") as f:
-        json.dump({"nparam": int(M.MLP_NPARAM), "params": [float(v) for v in params], "meta": meta or {}}, f)
+        json.dump(d, f)
+
+
+def load_checkpoint(path):
+    """(params, m1, m2, step) from a file written by save(..., state=...)."""
+    with open(path) as f:
+        d = json.load(f)
+    if "adam" not in d:
+        raise ValueError(f"{path} holds weights only, no optimizer state")
+    arrs = [np.array(v, dtype=np.float32) for v in (d["params"], d["adam"]["m1"], d["adam"]["m2"])]
+    if any(a.size != M.MLP_NPARAM for a in arrs):
+        raise ValueError(f"{path}: expected {M.MLP_NPARAM} values per array")
+    return arrs[0], arrs[1], arrs[2], int(d["adam"]["step"])
 
 
 def load(path=WEIGHTS) -> np.ndarray:

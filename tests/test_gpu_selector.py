@@ -92,6 +92,37 @@ def test_training_reduces_loss():
     assert acc > 0.9
 
 
+def test_training_resumes_from_checkpoint_bit_for_bit(tmp_path):
+    """20 Adam steps in one run equal 10 steps, a checkpoint through a file
+    (weights, both moments, step) and 10 more steps on a fresh trainer, bit
+    for bit; the state setter refuses bad moments and sizes."""
+    import paper_2408_04440_amd.selector as S
+
+    X, y = synth.features_toy(384, 33)
+    p_all, _, st_all = S.train(X, y, steps=20, lr=3e-3, alpha=2.0, return_state=True)
+    _, _, st10 = S.train(X, y, steps=10, lr=3e-3, alpha=2.0, return_state=True)
+    f = tmp_path / "ck.json"
+    S.save(st10[0], str(f), state=st10)
+    p_res, _, st_res = S.train(X, y, steps=10, lr=3e-3, alpha=2.0, state=S.load_checkpoint(str(f)),
+                               return_state=True)
+    assert st10[3] == 10 and st_res[3] == 20 == st_all[3]
+    assert np.array_equal(p_res, p_all)
+    assert np.array_equal(st_res[1], st_all[1]) and np.array_equal(st_res[2], st_all[2])
+    mod = M()
+    m = mod.mpchol_mlp_create()
+    try:
+        bad = st10[2].copy()
+        bad[5] = -1.0
+        with pytest.raises(mod.MpcholError):
+            mod.mpchol_mlp_set_state(m, st10[0], st10[1], bad, 10)
+        with pytest.raises(mod.MpcholError):
+            mod.mpchol_mlp_set_state(m, st10[0], st10[1], st10[2], -1)
+        with pytest.raises(ValueError):
+            mod.mpchol_mlp_set_state(m, st10[0][:10], st10[1], st10[2], 10)
+    finally:
+        mod.mpchol_mlp_destroy(m)
+
+
 def _features_ref(fro2, amax, tot, eps, n, b):
     nt = fro2.shape[0]
     Lw = int(np.floor(np.sqrt(n - 1))) + 1

@@ -46,6 +46,27 @@ def test_class_weights_and_roundtrip(tmp_path):
     assert json.load(open(f))["meta"] == {"k": 1}
 
 
+def test_checkpoint_roundtrip(tmp_path):
+    """A checkpoint holds the weights, Adam's two moments and the step count,
+    and reads back exactly (float32 values through JSON); a weights-only file
+    is refused as a checkpoint."""
+    from paper_2408_04440_amd import selector as S
+
+    p = S.he_uniform_init(7)
+    m1 = (np.arange(p.size, dtype=np.float32) - 2000.0) * np.float32(1.0e-7)
+    m2 = np.abs(m1) * np.float32(3.3e-3) + np.float32(1e-30)
+    f = tmp_path / "ck.json"
+    S.save(p, str(f), meta={"k": 2}, state=(p, m1, m2, 123))
+    q, n1, n2, st = S.load_checkpoint(str(f))
+    assert st == 123 and q.dtype == np.float32
+    assert np.array_equal(q, p) and np.array_equal(n1, m1) and np.array_equal(n2, m2)
+    assert np.array_equal(S.load(str(f)), p)
+    g = tmp_path / "w.json"
+    S.save(p, str(g))
+    with pytest.raises(ValueError):
+        S.load_checkpoint(str(g))
+
+
 def test_synth_layout():
     L = 7
     l, m = synth.sh_degrees(L), synth.sh_orders(L)
