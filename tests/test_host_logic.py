@@ -103,6 +103,31 @@ def test_bench_solve_backward_error():
     assert abs(got - want) <= 1e-6 * want
 
 
+# ---------------------------------------------------------------- the oracle under host sanitizers
+def test_oracle_under_address_and_undefined_behavior_sanitizers():
+    """oracle.c built with AddressSanitizer (leak detection on) and
+    UndefinedBehaviorSanitizer, every entry point driven on small cases with a
+    ragged last tile (tests/oracle_sanitize_check.c): no invalid access, leak
+    or undefined operation, and the driver's checks hold."""
+    import shutil
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    out = os.path.join(root, "_build", "oracle_sanitize_check")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    subprocess.check_call(["gcc", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-ffp-contract=off", "-fopenmp",
+                           os.path.join(root, "oracle", "oracle.c"), os.path.join(root, "tests", "oracle_sanitize_check.c"),
+                           "-lm", "-o", out])
+    env = dict(os.environ, OMP_NUM_THREADS="2", ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([out], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.strip() == "ok" and "Sanitizer" not in r.stderr
+
+
 # ---------------------------------------------------------------- residue arithmetic of the INT8-emulated FP64 products
 def _ozaki_host_check():
     """Build (hipcc, host code) the CPU driver of the library's residue helpers."""
