@@ -18,56 +18,84 @@ __device__ inline double source_at(const Tiles &T, const Source &S, int I, int J
     return v;
 }
 
-// 128 x 128 output block per workgroup, 16 waves of 32 x 32 (the FP64
-// update's shape), K staged 16 columns at a time through LDS.
-constexpr int RB = 128, RK = 16, RLD = RB + 16, RW = 4, RNT = 64 * RW * RW, RPER = RK * RB / RNT;
+// 128 x 128 output block per workgroup, 8 waves of 64 x 32 (two blocks share
+// a compute unit: 144 KiB of LDS for the two, at most 128 registers a lane),
+// K staged 16 columns at a time through LDS.
+constexpr int RB = 128, RK = 16, RLD = RB + 16, RWM = 2, RWN = 4, RNT = 64 * RWM * RWN, RPER = RK * RB / RNT;
+constexpr int RMB = RB / RWM / 16, RNB = RB / RWN / 16;  // MFMA tiles per wave: 4 x 2
+static_assert(RNT <= 2 * RK * RLD, "the reduction reuses the A staging buffers");
 
-__global__ __launch_bounds__(RNT) void residual_kernel(Tiles T, Source S, const int32_t *items, double *partial)
+__global__ __launch_bounds__(RNT) __attribute__((amdgpu_waves_per_eu(4))) void residual_kernel(Tiles T, Source S,
+                                                                                              const int32_t *items,
+                                                                                              double *partial)
 {
     __shared__ double As[2][RK][RLD], Bs[2][RK][RLD];
-    __shared__ double red[RNT];
     const int b = T.b, nsub = b / RB;
     const int item = blockIdx.x / (nsub * nsub), rem = blockIdx.x % (nsub * nsub);
     const int tm = rem % nsub, tn = rem / nsub;
     const int32_t it = items[item];
     const int I = it >> 16, J = it & 0xFFFF;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % RW, wn = wave / RW, gi = lane & 15, gg = lane >> 4;
-    constexpr int WT = RB / RW;  // 32
-    double4_t acc[2][2];
+    const int wm = wave % RWM, wn = wave / RWM, gi = lane & 15, gg = lane >> 4;
+    constexpr int WTM = RB / RWM, WTN = RB / RWN;  // 64, 32
+    double4_t acc[RMB][RNB];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < RMB; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < RNB; ++n) acc[m][n] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
     const bool skip = (I == J && tn > tm);
     if (!skip) {
         const int nkt = b / RK;
-        double ra[RPER], rb[RPER];
+        // raw stored codes in registers (the loads stay in flight across the
+        // current slice's products), widened to FP64 only when staged
+        uint64_t ra[RPER], rb[RPER];
         for (int K = 0; K <= J; ++K) {
             const int ca = (I == K) ? P64 : T.map[I + (int64_t)K * T.nt];
             const int cbc = (J == K) ? P64 : T.map[J + (int64_t)K * T.nt];
             const int ta = T.tscale[I + (int64_t)K * T.nt], tb = T.tscale[J + (int64_t)K * T.nt];
             const char *sa = T.slots + tile_index(I, K) * T.slot_bytes;
             const char *sb = T.slots + tile_index(J, K) * T.slot_bytes;
-            auto gload = [&](int kt) {
+            auto fetch = [&](const char *tile, int cls, int row0, int kt, uint64_t(&raw)[RPER]) {
+                int off[RPER];  // within one tile: below b * b
 #pragma unroll
                 for (int c = 0; c < RPER; ++c) {
-                    int e = tid + RNT * c;  // 0 .. RK*RB-1
-                    int r = e % RB, col = e / RB;
-                    int64_t off = (int64_t)(tm * RB + r) + (int64_t)(kt * RK + col) * b;
-                    int64_t offb = (int64_t)(tn * RB + r) + (int64_t)(kt * RK + col) * b;
-                    ra[c] = load_stored(sa, ca, T.lo16, ta, off);
-                    rb[c] = load_stored(sb, cbc, T.lo16, tb, offb);
+                    const int e = tid + RNT * c, r = e % RB, col = e / RB;
+                    off[c] = (row0 + r) + (kt * RK + col) * b;
                 }
+                switch (cls) {
+                case P64:
+#pragma unroll
+                    for (int c = 0; c < RPER; ++c) raw[c] = ((const uint64_t *)tile)[off[c]];
+                    break;
+                case P32:
+#pragma unroll
+                    for (int c = 0; c < RPER; ++c) raw[c] = ((const uint32_t *)tile)[off[c]];
+                    break;
+                case P16:
+#pragma unroll
+                    for (int c = 0; c < RPER; ++c) raw[c] = ((const uint16_t *)tile)[off[c]];
+                    break;
+                default:
+#pragma unroll
+                    for (int c = 0; c < RPER; ++c) raw[c] = ((const uint8_t *)tile)[off[c]];
+                    break;
+                }
+            };
+            auto widen = [&](uint64_t raw, int cls, int t) -> double {
+                return cls == P64 ? __longlong_as_double((long long)raw) : decode_class((uint32_t)raw, cls, T.lo16, t);
+            };
+            auto gload = [&](int kt) {
+                fetch(sa, ca, tm * RB, kt, ra);
+                fetch(sb, cbc, tn * RB, kt, rb);
             };
             auto sstore = [&](int buf) {
 #pragma unroll
                 for (int c = 0; c < RPER; ++c) {
                     int e = tid + RNT * c;
                     int r = e % RB, col = e / RB;
-                    As[buf][col][r] = ra[c];
-                    Bs[buf][col][r] = rb[c];
+                    As[buf][col][r] = widen(ra[c], ca, ta);
+                    Bs[buf][col][r] = widen(rb[c], cbc, tb);
                 }
             };
             gload(0);
@@ -78,15 +106,15 @@ __global__ __launch_bounds__(RNT) void residual_kernel(Tiles T, Source S, const 
                 if (kt + 1 < nkt) gload(kt + 1);
 #pragma unroll
                 for (int s = 0; s < RK / 4; ++s) {
-                    double fa[2], fb[2];
+                    double fa[RMB], fb[RNB];
 #pragma unroll
-                    for (int m = 0; m < 2; ++m) fa[m] = As[cur][s * 4 + gg][wm * WT + m * 16 + gi];
+                    for (int m = 0; m < RMB; ++m) fa[m] = As[cur][s * 4 + gg][wm * WTM + m * 16 + gi];
 #pragma unroll
-                    for (int n = 0; n < 2; ++n) fb[n] = Bs[cur][s * 4 + gg][wn * WT + n * 16 + gi];
+                    for (int n = 0; n < RNB; ++n) fb[n] = Bs[cur][s * 4 + gg][wn * WTN + n * 16 + gi];
 #pragma unroll
-                    for (int m = 0; m < 2; ++m)
+                    for (int m = 0; m < RMB; ++m)
 #pragma unroll
-                        for (int n = 0; n < 2; ++n)
+                        for (int n = 0; n < RNB; ++n)
                             acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[m], fb[n], acc[m][n], 0, 0, 0);
                 }
                 if (kt + 1 < nkt) sstore(cur ^ 1);
@@ -97,12 +125,12 @@ __global__ __launch_bounds__(RNT) void residual_kernel(Tiles T, Source S, const 
     double s2 = 0.0;
     if (!skip) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < RMB; ++m)
 #pragma unroll
-            for (int n = 0; n < 2; ++n)
+            for (int n = 0; n < RNB; ++n)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    int r = tm * RB + wm * WT + m * 16 + acc_row<double>(gg, v), c = tn * RB + wn * WT + n * 16 + gi;
+                    int r = tm * RB + wm * WTM + m * 16 + acc_row<double>(gg, v), c = tn * RB + wn * WTN + n * 16 + gi;
                     int64_t i = (int64_t)I * b + r, j = (int64_t)J * b + c;
                     if (i >= T.n || j >= T.n || i < j) continue;
                     double res = source_at(T, S, I, J, r, c) - acc[m][n][v];
@@ -110,6 +138,9 @@ __global__ __launch_bounds__(RNT) void residual_kernel(Tiles T, Source S, const 
                     s2 += w * res * res;
                 }
     }
+    // every wave is past the K loop's last barrier: the A staging buffers
+    // are free for the reduction
+    double *red = &As[0][0][0];
     red[tid] = s2;
     __syncthreads();
     for (int w = RNT / 2; w > 0; w >>= 1) {
