@@ -259,6 +259,9 @@ def main():
     ap.add_argument("--lo64", default="fp64", choices=["fp64", "int8"],
                     help="FP64-class update products beyond the FP64 band: FP64 MFMA, or exact integer products "
                          "from INT8 residues (the plain FP64 comparison path always uses the FP64 MFMA)")
+    ap.add_argument("--lo8", default="tile", choices=["tile", "mx"],
+                    help="FP8-class copies: one power-of-two scale per tile, or an E8M0 scale per 32 K elements of "
+                         "a row applied inside the block-scaled FP8 MFMA")
     ap.add_argument("--band-variant", type=int, default=None, choices=[1, 2, 3],
                     help="band rule variant: 1 DP/SP, 2 DP/SP/HP, 3 DP/HP")
     ap.add_argument("--rule", default=None, choices=["norm", "learned", "fp64", "band", "learned_unverified"],
@@ -334,6 +337,7 @@ def main():
     extra = {} if args.band_variant is None else {"band_variant": args.band_variant}
     extra["lo32"] = M.LO32_BF16X3 if args.lo32 == "bf16x3" else M.LO32_FP32
     extra["lo64"] = M.LO64_INT8 if args.lo64 == "int8" else M.LO64_FP64
+    extra["lo8"] = M.LO8_MX if args.lo8 == "mx" else M.LO8_TILE
     h = M.mpchol_create(n, tile, stream=stream, lo16=cfg["lo16"], allowed=cfg["allowed"], profile=1,
                         verify=2 if need_w else 0, verify_eps=eps, **extra)
     M.mpchol_set_generator(h, sigma, x, rho, nugget)
@@ -480,12 +484,13 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if rule == M.RULE_FP64 else ("f64+int8crt" if args.lo64 == "int8" else "f64") + "/" +
                  ("bf16x3-f32acc" if args.lo32 == "bf16x3" else "f32") + "/" +
-                 ("bf16" if cfg["lo16"] else "f16") + ("/fp8-e4m3" if cfg["allowed"] & 8 else ""),
+                 ("bf16" if cfg["lo16"] else "f16") +
+                 (("/fp8-e4m3" + ("-mx32" if args.lo8 == "mx" else "")) if cfg["allowed"] & 8 else ""),
         "data": "synthetic",
         "config": {"workload": f"SH covariance L={L} (N={n}), tile {tile}, rho={rho}, nugget 1e-8, "
                                f"{[k for k, v in RULES.items() if v == rule][0]} rule eps={eps}, classes {cfg['label']}",
                    "N": n, "tile": tile, "nt": nt, "rho": rho, "eps": eps, "fp32_class": args.lo32,
-                   "fp64_class": args.lo64,
+                   "fp64_class": args.lo64, "fp8_scales": "per 32 K elements (E8M0)" if args.lo8 == "mx" else "per tile",
                    "step": "generate+norms+map+factor+logdet" + ("+1000 draws" if cfg["draws"] else "")
                            + (f"+solve({cfg['rhs']} rhs)" if cfg["rhs"] else "")},
         "t_factor_ms": round(t_med, 2),

@@ -59,6 +59,9 @@ extern "C" {
 /* how FP64-class tile products are formed */
 #define MPCHOL_LO64_FP64 0 /* on the FP64 MFMA */
 #define MPCHOL_LO64_INT8 1 /* exact integer products from INT8 residues (see mpchol_opts.lo64) */
+/* how the FP8-class operands are scaled */
+#define MPCHOL_LO8_TILE 0 /* one power-of-two scale per panel tile, applied to the accumulated product */
+#define MPCHOL_LO8_MX 1   /* one E8M0 scale per 32 consecutive K elements of a row (see mpchol_opts.lo8) */
 
 /* precision-map rules */
 #define MPCHOL_RULE_FP64 0    /* every tile FP64 (the plain FP64 path) */
@@ -98,7 +101,19 @@ typedef struct mpchol_opts {
                             remainder theorem, rounded once to FP64 and scaled back; the FP64 work tile
                             accumulates as before.  SYRK, the tiles within `band` and the plain FP64 path
                             (rule FP64) stay on the FP64 MFMA.  Tiles up to 1024 (else MPCHOL_EUNSUPPORTED
-                            at create); needs 4 NT tile^2 15 bytes more panel memory.  Default FP64. */
+                            at create); needs 6 NT tile^2 15 bytes more panel memory (six panel copy
+                            sets).  Default FP64. */
+    int32_t lo8;         /* scaling of the FP8-class products: MPCHOL_LO8_TILE (the E4M3 copy of a panel
+                            tile takes one power-of-two scale from the tile's largest |value|, and the
+                            accumulated product is scaled back) or MPCHOL_LO8_MX -- block scaling in the
+                            manner of the OCP Microscaling formats: every run of 32 consecutive elements of
+                            a row of the copy (the K direction of the products) takes its own power-of-two
+                            scale 2^-t, t the largest integer with (block max |value|) 2^t <= 448 (no
+                            element saturates; t clamped to [-127, 127]), stored as the E8M0 byte 127 - t
+                            and applied inside the block-scaled FP8 MFMA.  Only the FP8 copies of the
+                            panel tiles change: stored FP8 tiles keep their per-tile scale, and the map
+                            rule prices the class with the same unit roundoff 2^-4.  Needs 6 NT tile^2 / 32
+                            bytes more panel memory.  Default TILE. */
 } mpchol_opts;
 
 typedef struct mpchol_stats {

@@ -86,7 +86,10 @@ def lib():
         L.orc_map_band.argtypes = [i64, i32, i32, C.c_uint, C.POINTER(C.c_uint8)]
         L.orc_mp_factor.restype = i64
         L.orc_mp_factor.argtypes = [i64, i64, dp, i64, C.POINTER(C.c_uint8), i32, dp, i64, C.POINTER(C.c_int32), i32, i32,
-                                    i32, i32]
+                                    i32, i32, i32]
+        L.orc_mx_block_exp.restype = i32
+        L.orc_mx_block_exp.argtypes = [d]
+        L.orc_mx_quantize.argtypes = [i64, i64, dp, i64, dp, i64, C.POINTER(C.c_int32)]
         L.orc_ozaki_gemm.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64]
         L.orc_ozaki_row_exp.restype = i32
         L.orc_ozaki_row_exp.argtypes = [dp, i64, i64]
@@ -268,14 +271,15 @@ def map_band(nt, band=1, variant=3, allowed=0xF):
     return out
 
 
-def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0, lo64=0, band=1):
+def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0, lo64=0, band=1, lo8=0):
     """O2: (Lhat, info, tscale) -- the tile algorithm replayed with explicit rounding.
 
     cmap is an nt x nt class map (lower part used; 0 FP64, 1 FP32, 2 16-bit, 3 FP8);
     order 0/1 sums the update products in increasing/decreasing order;
     lo32 = 1 forms FP32-class products from three-way BF16 splits;
     lo64 = 1 forms the FP64-class products of tiles farther than `band` from
-    the diagonal as exact integer products of row-scaled panels (ozaki_gemm).
+    the diagonal as exact integer products of row-scaled panels (ozaki_gemm);
+    lo8 = 1 block-scales the FP8 copies of the panel tiles (mx_quantize).
     """
     A = _fortran(A)
     n = A.shape[0]
@@ -285,8 +289,27 @@ def mp_factor(A, b, cmap, lo16=F16, order=0, lo32=0, lo64=0, band=1):
     Lh = np.zeros((n, n), order="F")
     ts = np.zeros((nt, nt), dtype=np.int32, order="F")
     info = lib().orc_mp_factor(n, b, _dp(A), n, cmap.ctypes.data_as(C.POINTER(C.c_uint8)), lo16, _dp(Lh), n,
-                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order), int(lo32), int(lo64), int(band))
+                               ts.ctypes.data_as(C.POINTER(C.c_int32)), int(order), int(lo32), int(lo64), int(band),
+                               int(lo8))
     return Lh, int(info), ts
+
+
+def mx_block_exp(amax):
+    """Exponent t of a block-scaled FP8 block with largest |value| amax: the
+    largest t with amax 2^t <= 448, clamped to [-127, 127] (0 for amax = 0)."""
+    return int(lib().orc_mx_block_exp(float(amax)))
+
+
+def mx_quantize(X):
+    """(values, texp): the block-scaled FP8 copy of X (rows x cols) -- per
+    row, every 32 consecutive elements (fewer in a row's last block) share a
+    power-of-two scale; texp[r, c // 32] are the block exponents."""
+    X = _fortran(X)
+    rows, cols = X.shape
+    out = np.zeros((rows, cols), order="F")
+    texp = np.zeros((rows, (cols + 31) // 32), dtype=np.int32, order="F")
+    lib().orc_mx_quantize(rows, cols, _dp(X), rows, _dp(out), rows, texp.ctypes.data_as(C.POINTER(C.c_int32)))
+    return out, texp
 
 
 def ozaki_gemm(A, B):

@@ -381,15 +381,55 @@ double orc_unit_roundoff(int fmt)
 /* Per-tile power-of-two scale for the narrow-range formats: the largest
  * integer t with amax * 2^t <= largest finite value.  FP16 and E4M3 are
  * scaled; FP64, FP32 and BF16 (FP32's exponent range) use t = 0, as does an
- * all-zero tile. */
+ * all-zero tile, and a tile whose maximum is not finite (no such t exists). */
 int orc_scale_exp(double amax, int fmt)
 {
-    if (!(fmt == ORC_F16 || fmt == ORC_E4M3) || !(amax > 0.0)) return 0;
+    if (!(fmt == ORC_F16 || fmt == ORC_E4M3) || !(amax > 0.0) || !isfinite(amax)) return 0;
     double maxf = (fmt == ORC_F16) ? 65504.0 : 448.0;
     int t = ilogb(maxf) - ilogb(amax);
     while (ldexp(amax, t) > maxf) --t;
     while (ldexp(amax, t + 1) <= maxf) ++t;
     return t;
+}
+
+/* ------------------------------------------------------------------------
+ * Block-scaled FP8 copies, after the OCP Microscaling formats: one shared
+ * power-of-two scale per block of 32 consecutive elements -- here the
+ * elements of a row along the K direction of the products that read the
+ * copy.  Block exponent: t = orc_scale_exp(block max |v|, E4M3) clamped to
+ * [-127, 127] (the range of an E8M0 scale), so no element saturates; each
+ * element becomes round_e4m3(round_f32(v 2^t)) and represents that code
+ * times 2^-t.  (The OCP recipe takes floor(log2 max) - 8 and saturates
+ * elements above 448; the choice here is the per-tile rule applied per
+ * block.)
+ * Pinned by: brute force of the exponent choice; exactness for values of at
+ * most four significant bits at any exponent per block; equality with the
+ * per-tile copy when every block holds the tile's maximum; the per-element
+ * E4M3 rounding bound.
+ * ---------------------------------------------------------------------- */
+int orc_mx_block_exp(double amax)
+{
+    int t = orc_scale_exp(amax, ORC_E4M3);
+    return t < -127 ? -127 : (t > 127 ? 127 : t);
+}
+
+/* X: rows x cols (column-major, leading dimension ld); the last block of a
+ * row is shorter when cols is not a multiple of 32.  out (leading dimension
+ * ldo) = the represented values of the copy; texp (optional)
+ * [r + (c / 32) * rows] = the block exponents. */
+void orc_mx_quantize(int64_t rows, int64_t cols, const double *X, int64_t ld, double *out, int64_t ldo, int32_t *texp)
+{
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t c0 = 0; c0 < cols; c0 += 32) {
+            const int64_t ce = c0 + 32 < cols ? c0 + 32 : cols;
+            double m = 0.0;
+            for (int64_t c = c0; c < ce; ++c)
+                if (fabs(X[r + c * ld]) > m) m = fabs(X[r + c * ld]);
+            int t = orc_mx_block_exp(m);
+            if (texp) texp[r + (c0 / 32) * rows] = t;
+            for (int64_t c = c0; c < ce; ++c)
+                out[r + c * ldo] = ldexp(orc_round((double)(float)ldexp(X[r + c * ld], t), ORC_E4M3), -t);
+        }
 }
 
 /* ------------------------------------------------------------------------
@@ -588,7 +628,10 @@ void orc_ozaki_gemm(int64_t m, int64_t n, int64_t k, const double *A, int64_t ld
  *       products with float adds (the split-product scheme of Henry, Tang and
  *       Heinecke, ARITH 2019, with the three smallest products dropped);
  *     16-bit/FP8-class GEMM: acc as above on the scaled copies,
- *       W = round_f32(W - acc * 2^-(t_I + t_J)).
+ *       W = round_f32(W - acc * 2^-(t_I + t_J));
+ *       with lo8 = 1 the FP8 copies are block-scaled (orc_mx_quantize over
+ *       the rows of each panel tile) and acc sums the float products of the
+ *       represented values, W = round_f32(W - acc).
  * order = 0 sums the update products in increasing c, order = 1 in
  * decreasing c: two valid executions whose difference calibrates how far
  * another summation order (the GPU's) may move the result.
@@ -613,7 +656,7 @@ float orc_split3(double v, int part)
 }
 
 int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const uint8_t *map, int lo16,
-                      double *Lhat, int64_t ldl, int32_t *tscale, int order, int lo32, int lo64, int band64)
+                      double *Lhat, int64_t ldl, int32_t *tscale, int order, int lo32, int lo64, int band64, int lo8)
 {
     int64_t nt = (n + b - 1) / b, np = nt * b;
     double *W = malloc(sizeof(double) * (size_t)np * np);
@@ -711,6 +754,10 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                         if (q == ORC_P32 && lo32)
                             for (int p = 0; p < 3; ++p) S3[p][(i0 + r) + (size_t)c * np] = orc_split3(cv, p);
                     }
+                if (q == ORC_P8 && lo8) {
+                    tq[I * 4 + q] = 0;
+                    orc_mx_quantize(b, b, W + IDX(i0, k0), np, C[q] + i0, np, NULL);
+                }
             }
             if (lo64)
                 for (int64_t r = 0; r < b; ++r) {
@@ -773,7 +820,7 @@ int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const 
                         }
                         for (int64_t r = 0; r < b; ++r) {
                             float w = (float)W[IDX(i0 + r, j0 + s)];
-                            if (cls == ORC_P32) w = w - acc32[r];
+                            if (cls == ORC_P32 || (cls == ORC_P8 && lo8)) w = w - acc32[r];
                             else w = w - ldexpf(acc32[r], -(tq[I * 4 + cls] + tq[J * 4 + cls]));
                             W[IDX(i0 + r, j0 + s)] = (double)w;
                         }

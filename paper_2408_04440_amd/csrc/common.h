@@ -65,11 +65,12 @@ __device__ inline float e4m3_to_f32(uint8_t c)
 
 // Largest integer t with amax * 2^t <= the format's largest finite value for
 // the scaled formats (FP16: 65504, E4M3: 448); 0 for FP64, FP32 and BF16
-// (BF16 has FP32's exponent range) and for amax == 0.
+// (BF16 has FP32's exponent range), for amax == 0 and for a maximum that is
+// not finite (no t exists; the codes then saturate or carry the NaN).
 __host__ __device__ inline bool class_scaled(int q, int lo16) { return q == P8 || (q == P16 && lo16 == LO16_F16); }
 __host__ __device__ inline int scale_exp(double amax, int q, int lo16)
 {
-    if (!class_scaled(q, lo16) || !(amax > 0.0)) return 0;
+    if (!class_scaled(q, lo16) || !(amax > 0.0) || !(amax <= 1.7976931348623157e308)) return 0;
     double maxf = (q == P8) ? 448.0 : 65504.0;
     int ea, em;
     frexp(amax, &ea);

@@ -268,7 +268,22 @@ template <> struct RM<RM_FP8> {
     {
         return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
     }
+    // block-scaled form: sa, sb are the E8M0 scales (value 2^(s - 127), in the
+    // low byte) of the 32 K elements this lane holds of its A row and B column
+    __device__ static inline float4_t mfma_mx(frag_t a, frag_t b, float4_t c, int sa, int sb)
+    {
+        return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
+    }
 };
+
+// The operand of one lane of the block-scaled FP8 instruction: bytes
+// 0 .. 15 and 64 .. 79 from p (a row of a 128-element K slice, offset 16 gg).
+__device__ inline i32x8 mx_frag(const uint8_t *p)
+{
+    const u32x4 lo = *(const u32x4 *)p, hi = *(const u32x4 *)(p + 64);
+    return (i32x8){(int32_t)lo[0], (int32_t)lo[1], (int32_t)lo[2], (int32_t)lo[3],
+                   (int32_t)hi[0], (int32_t)hi[1], (int32_t)hi[2], (int32_t)hi[3]};
+}
 
 template <int KIND, int BM, int BN, int BK, int WM = 2, int WN = 2>
 struct RMShape {
@@ -281,16 +296,23 @@ struct RMShape {
     static constexpr int CA = (CHA + NTH - 1) / NTH, CB = (CHB + NTH - 1) / NTH;
     static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;
     static constexpr size_t SMEM = (size_t)2 * (BM + BN) * LDB;
+    static constexpr size_t SMEM_MX = SMEM + (size_t)2 * (BM + BN) * 4;  // + one scale word per row and buffer
     static_assert((CHA % NTH == 0 || CHA < NTH) && (CHB % NTH == 0 || CHB < NTH), "load split");
     static_assert(BK % RM<KIND>::KSTEP == 0 && MB >= 1 && NB >= 1, "shape");
 };
 
-template <int KIND, int BM, int BN, int BK, int WM = 2, int WN = 2>
+// MX (FP8 only): SA and SB hold E8M0 block scales, K / 32 bytes per row of
+// A and of B (row-major, 4-byte aligned rows); a slice of BK = 128 spans four
+// blocks, one 32-bit word per row, staged through LDS beside the codes.  The
+// lane that holds K elements 32 gg .. 32 gg + 31 of a row passes byte gg.
+template <int KIND, int BM, int BN, int BK, int WM = 2, int WN = 2, bool MX = false>
 __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int64_t lda,
                                 const typename RM<KIND>::T *__restrict__ B, int64_t ldb, int K,
                                 float4_t (&acc)[RMShape<KIND, BM, BN, BK, WM, WN>::MB][RMShape<KIND, BM, BN, BK, WM, WN>::NB],
-                                uint8_t *smem)
+                                uint8_t *smem, const uint8_t *__restrict__ SA = nullptr,
+                                const uint8_t *__restrict__ SB = nullptr)
 {
+    static_assert(!MX || (KIND == RM_FP8 && BK == 128 && BM + BN <= 64 * WM * WN), "MX: one scale word per row and slice");
     typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
     typedef typename RM<KIND>::T T;
     typedef typename RM<KIND>::frag_t F;
@@ -299,21 +321,32 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
     const int gi = lane & 15, gg = lane >> 4;
     uint8_t *As = smem;                         // [2][BM][LDB]
     uint8_t *Bs = smem + 2 * BM * S::LDB;       // [2][BN][LDB]
+    uint32_t *Ss = (uint32_t *)(smem + 2 * (BM + BN) * S::LDB);  // MX: [2][BM + BN] scale words
     u32x4 ra[S::CA], rb[S::CB];
+    uint32_t rs = 0;
     const int nk = K / BK;
+    // every thread stages whole chunks (no partial rounds): the MX variant
+    // drops the always-true bounds tests so that its products and the next
+    // slice's stores stay in one block, in that order
+    constexpr bool FULL = MX && S::CHA % S::NTH == 0 && S::CHB % S::NTH == 0 && BM + BN == S::NTH;
 
     auto gload = [&](int kt) {
 #pragma unroll
         for (int c = 0; c < S::CA; ++c) {
             int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            if (ch < S::CHA) ra[c] = *(const u32x4 *)((const uint8_t *)(A + (int64_t)row * lda + kt * BK) + cb);
+            if (FULL || ch < S::CHA) ra[c] = *(const u32x4 *)((const uint8_t *)(A + (int64_t)row * lda + kt * BK) + cb);
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
             int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            if (ch < S::CHB) rb[c] = *(const u32x4 *)((const uint8_t *)(B + (int64_t)row * ldb + kt * BK) + cb);
+            if (FULL || ch < S::CHB) rb[c] = *(const u32x4 *)((const uint8_t *)(B + (int64_t)row * ldb + kt * BK) + cb);
+        }
+        if constexpr (MX) {
+            const uint32_t *src = tid < BM ? (const uint32_t *)SA + (int64_t)tid * nk
+                                           : (const uint32_t *)SB + (int64_t)(tid - BM) * nk;
+            if (FULL || tid < BM + BN) rs = src[kt];
         }
     };
     auto sstore = [&](int buf) {
@@ -321,13 +354,16 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
         for (int c = 0; c < S::CA; ++c) {
             int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            if (ch < S::CHA) *(u32x4 *)(As + (buf * BM + row) * S::LDB + cb) = ra[c];
+            if (FULL || ch < S::CHA) *(u32x4 *)(As + (buf * BM + row) * S::LDB + cb) = ra[c];
         }
 #pragma unroll
         for (int c = 0; c < S::CB; ++c) {
             int ch = tid + S::NTH * c;
             int row = ch / S::CPR, cb = (ch % S::CPR) * 16;
-            if (ch < S::CHB) *(u32x4 *)(Bs + (buf * BN + row) * S::LDB + cb) = rb[c];
+            if (FULL || ch < S::CHB) *(u32x4 *)(Bs + (buf * BN + row) * S::LDB + cb) = rb[c];
+        }
+        if constexpr (MX) {
+            if (FULL || tid < BM + BN) Ss[buf * (BM + BN) + tid] = rs;
         }
     };
 
@@ -348,17 +384,49 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
             constexpr int KS = RM<KIND>::KSTEP;  // K per instruction; KS / 4 per lane
             const int kb = (s * KS + (KS / 4) * gg) * (int)sizeof(T);
             F fa[S::MB], fb[S::NB];
+            if constexpr (MX) {
+                // the block-scaled instruction splits K into two halves of 64:
+                // lane group gg passes K elements 16 gg .. 16 gg + 15 of each
+                // half, and block b (K 32 b .. 32 b + 31) takes lane group b's
+                // scale; so each lane reads those two 16-byte pieces of its row
+                // and passes the scale of block gg
 #pragma unroll
-            for (int m = 0; m < S::MB; ++m) fa[m] = *(const F *)(as + m * 16 * S::LDB + kb);
+                for (int m = 0; m < S::MB; ++m) fa[m] = mx_frag(as + m * 16 * S::LDB + 16 * gg);
 #pragma unroll
-            for (int n = 0; n < S::NB; ++n) fb[n] = *(const F *)(bs + n * 16 * S::LDB + kb);
+                for (int n = 0; n < S::NB; ++n) fb[n] = mx_frag(bs + n * 16 * S::LDB + 16 * gg);
+            } else {
 #pragma unroll
-            for (int m = 0; m < S::MB; ++m)
+                for (int m = 0; m < S::MB; ++m) fa[m] = *(const F *)(as + m * 16 * S::LDB + kb);
 #pragma unroll
-                for (int n = 0; n < S::NB; ++n) acc[m][n] = RM<KIND>::mfma(fa[m], fb[n], acc[m][n]);
+                for (int n = 0; n < S::NB; ++n) fb[n] = *(const F *)(bs + n * 16 * S::LDB + kb);
+            }
+            if constexpr (MX) {
+                const uint32_t *ss = Ss + cur * (BM + BN);
+                int sa[S::MB], sb[S::NB];
+#pragma unroll
+                for (int m = 0; m < S::MB; ++m) sa[m] = (ss[wm * (BM / WM) + m * 16 + gi] >> (8 * gg)) & 0xff;
+#pragma unroll
+                for (int n = 0; n < S::NB; ++n) sb[n] = (ss[BM + wn * (BN / WN) + n * 16 + gi] >> (8 * gg)) & 0xff;
+#pragma unroll
+                for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                    for (int n = 0; n < S::NB; ++n) acc[m][n] = RM<KIND>::mfma_mx(fa[m], fb[n], acc[m][n], sa[m], sb[n]);
+                // keep the products ahead of the next slice's LDS stores: left to
+                // itself the compiler sinks them below those stores' wait for the
+                // global loads and the barrier, and nothing overlaps the loads
+                __builtin_amdgcn_sched_barrier(0);
+            } else {
+#pragma unroll
+                for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                    for (int n = 0; n < S::NB; ++n) acc[m][n] = RM<KIND>::mfma(fa[m], fb[n], acc[m][n]);
+            }
         }
         __builtin_amdgcn_s_setprio(0);
-        if (kt + 1 < nk) sstore(cur ^ 1);
+        // (FULL: on the last slice this rewrites the other buffer, which no
+        // wave reads any more, with registers already staged -- harmless, and
+        // it leaves no branch for the products to sink past)
+        if (FULL || kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
 }

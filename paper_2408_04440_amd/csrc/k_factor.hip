@@ -333,10 +333,11 @@ void update_cm_kernel(Tiles Tt, const T *panel0, const T *panel1, const int32_t 
 template <typename T> struct PanelSet {
     const T *p[4];
     const int32_t *s[4];  // scale exponents (class q copy of tile I at s[h][I * 4 + q]); unused for the split copies
+    const uint8_t *x[4];  // block-scaled FP8: E8M0 block scales of the copies (Panel::p8x)
     int n;
 };
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, bool MX = false>
 __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, PanelSet<typename RM<KIND>::T> ps, int q,
                                                                  const int32_t *items)
 {
@@ -357,39 +358,52 @@ __global__ __launch_bounds__(64 * WM * WN) void update_rm_kernel(Tiles Tt, Panel
     for (int m = 0; m < S::MB; ++m)
 #pragma unroll
         for (int n = 0; n < S::NB; ++n) acc[m][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    // Scaled copies: the product of step h is acc * 2^-(t_I + t_J) with its own
-    // exponent sum.  The steps are taken in decreasing exponent sum (smallest
-    // values first); before each later step the accumulator is rescaled down
-    // to that step's exponent sum, which is exact and cannot overflow, and
-    // the step's product then adds at that scale.
-    int ord[4], ts[4];
-    for (int h = 0; h < ps.n; ++h) {
-        const int t = ps.s[h][I * 4 + q] + ps.s[h][J * 4 + q];
-        int pos = h;
-        while (pos > 0 && ts[pos - 1] < t) {  // insertion by decreasing t (stable)
-            ts[pos] = ts[pos - 1];
-            ord[pos] = ord[pos - 1];
-            --pos;
-        }
-        ts[pos] = t;
-        ord[pos] = h;
-    }
-    int tsum = ts[0];
+    int tsum = 0;
+    if constexpr (MX) {
+        // block-scaled copies: the MFMA applies every block's scales, so the
+        // steps' products add at their own values
+        const int64_t xb = bb / 32, xrow = b / 32;
 #pragma nounroll
-    for (int h = 0; h < ps.n; ++h) {
-        const T *pn = ps.p[ord[h]];
-        if (h) {
-            const int t2 = ts[h];
-#pragma unroll
-            for (int m = 0; m < S::MB; ++m)
-#pragma unroll
-                for (int n = 0; n < S::NB; ++n)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[m][n][v] = ldexpf(acc[m][n][v], t2 - tsum);
-            tsum = t2;
+        for (int h = 0; h < ps.n; ++h)
+            rm_block<KIND, BM, BN, BK, WM, WN, true>(ps.p[h] + I * bb + (int64_t)tm * BM * b, b,
+                                                     ps.p[h] + J * bb + (int64_t)tn * BN * b, b, b, acc,
+                                                     (uint8_t *)smem_raw, ps.x[h] + I * xb + (int64_t)tm * BM * xrow,
+                                                     ps.x[h] + J * xb + (int64_t)tn * BN * xrow);
+    } else {
+        // Scaled copies: the product of step h is acc * 2^-(t_I + t_J) with its own
+        // exponent sum.  The steps are taken in decreasing exponent sum (smallest
+        // values first); before each later step the accumulator is rescaled down
+        // to that step's exponent sum, which is exact and cannot overflow, and
+        // the step's product then adds at that scale.
+        int ord[4], ts[4];
+        for (int h = 0; h < ps.n; ++h) {
+            const int t = ps.s[h][I * 4 + q] + ps.s[h][J * 4 + q];
+            int pos = h;
+            while (pos > 0 && ts[pos - 1] < t) {  // insertion by decreasing t (stable)
+                ts[pos] = ts[pos - 1];
+                ord[pos] = ord[pos - 1];
+                --pos;
+            }
+            ts[pos] = t;
+            ord[pos] = h;
         }
-        rm_block<KIND, BM, BN, BK, WM, WN>(pn + I * bb + (int64_t)tm * BM * b, b, pn + J * bb + (int64_t)tn * BN * b, b,
-                                           b, acc, (uint8_t *)smem_raw);
+        tsum = ts[0];
+#pragma nounroll
+        for (int h = 0; h < ps.n; ++h) {
+            const T *pn = ps.p[ord[h]];
+            if (h) {
+                const int t2 = ts[h];
+#pragma unroll
+                for (int m = 0; m < S::MB; ++m)
+#pragma unroll
+                    for (int n = 0; n < S::NB; ++n)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[m][n][v] = ldexpf(acc[m][n][v], t2 - tsum);
+                tsum = t2;
+            }
+            rm_block<KIND, BM, BN, BK, WM, WN>(pn + I * bb + (int64_t)tm * BM * b, b,
+                                               pn + J * bb + (int64_t)tn * BN * b, b, b, acc, (uint8_t *)smem_raw);
+        }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave % WM, wn = wave / WM, gi = lane & 15, gg = lane >> 4;
@@ -488,19 +502,20 @@ static void launch_cm(const Tiles &T_, const T *panel0, const T *panel1, const i
     k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, panel0, panel1, items);
 }
 
-template <int KIND, int BM, int BN, int BK, int WM, int WN>
+template <int KIND, int BM, int BN, int BK, int WM, int WN, bool MX = false>
 static void launch_rm(const Tiles &T_, const PanelSet<typename RM<KIND>::T> &ps, int q, const int32_t *items,
                       int nitems, hipStream_t st)
 {
     typedef RMShape<KIND, BM, BN, BK, WM, WN> S;
-    auto k = update_rm_kernel<KIND, BM, BN, BK, WM, WN>;
+    constexpr size_t smem = MX ? S::SMEM_MX : S::SMEM;
+    auto k = update_rm_kernel<KIND, BM, BN, BK, WM, WN, MX>;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::SMEM);
+        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         attr = true;
     }
     const int64_t grid = (int64_t)nitems * (T_.b / BM) * (T_.b / BN);
-    k<<<(unsigned)grid, S::NTH, S::SMEM, st>>>(T_, ps, q, items);
+    k<<<(unsigned)grid, S::NTH, smem, st>>>(T_, ps, q, items);
 }
 
 // Block shapes per class from a sweep on MI355X (1024 x 1024 tiles):
@@ -555,8 +570,10 @@ void launch_update(const Tiles &T, const Panel *const *Ps, int npan, int q, cons
         for (int h = 0; h < npan; ++h) {
             ps.p[h] = Ps[h]->p8;
             ps.s[h] = Ps[h]->pscale;
+            ps.x[h] = Ps[h]->p8x;
         }
-        launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, ps, q, items, nitems, st);
+        if (T.lo8) launch_rm<RM_FP8, 128, 128, 128, 2, 2, true>(T, ps, q, items, nitems, st);
+        else launch_rm<RM_FP8, 128, 128, 128, 2, 2>(T, ps, q, items, nitems, st);
         break;
     }
     }

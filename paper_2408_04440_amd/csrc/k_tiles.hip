@@ -94,11 +94,14 @@ __global__ __launch_bounds__(256) void copy_matrix_kernel(Tiles T, const double 
 // rounded code of (float)X with t from max|(float)X| -- and every class q
 // in qmask[I] gets its copy: FP64 S, FP32 (float)S (or, with the split
 // products, its three BF16 parts), 16-bit/FP8 the code of S with the copy's
-// own scale (row-major for the 16-bit, 8-bit and split copies).
+// own scale (row-major for the 16-bit, 8-bit and split copies).  With
+// block-scaled FP8 (lo8 MX) every 32 columns of a row of the FP8 copy take
+// their own scale from their own largest |S|, written as the E8M0 byte 127 - t.
 __global__ __launch_bounds__(256) void convert_kernel(Tiles T, Panel P, int k, const uint8_t *qmask)
 {
     __builtin_amdgcn_s_setprio(3);  // the panel chain: issue ahead of update waves sharing the SIMD
     __shared__ double xs[64][65];  // xs[c][r]
+    __shared__ int xt[64][2];      // lo8 MX: scale exponent of row r, 32-column half h of the sub-tile
     const int b = T.b, nsub = b / 64;
     const int I = k + 1 + blockIdx.y;
     const int sr = blockIdx.x % nsub, sc = blockIdx.x / nsub;
@@ -150,14 +153,27 @@ __global__ __launch_bounds__(256) void convert_kernel(Tiles T, Panel P, int k, c
         if ((mask & 2) && !T.lo32) P.p32[(int64_t)I * bb + off] = (float)Sv;
     }
     const bool split = (mask & 2) && T.lo32;
+    const bool mx = (mask & 8) && T.lo8;
     if ((mask & 12) || split) {
         __syncthreads();
+        if (mx) {
+            if (threadIdx.x < 128) {
+                const int r = threadIdx.x & 63, h = threadIdx.x >> 6;
+                double a = 0.0;
+                for (int c = 0; c < 32; ++c) a = fmax(a, fabs(xs[h * 32 + c][r]));
+                const int t = min(max(scale_exp(a, P8, lo16), -127), 127);  // 0 for an all-zero block
+                xt[r][h] = t;
+                P.p8x[(int64_t)I * (bb / 32) + (int64_t)(sr * 64 + r) * (b / 32) + sc * 2 + h] = (uint8_t)(127 - t);
+            }
+            __syncthreads();
+        }
         for (int e = threadIdx.x; e < 4096; e += 256) {
             int c = e & 63, r = e >> 6;
             double Sv = xs[c][r];
             int64_t roff = (int64_t)(sr * 64 + r) * b + (sc * 64 + c);
             if (mask & 4) P.p16[(int64_t)I * bb + roff] = (uint16_t)encode_class(Sv, P16, lo16, tq[P16]);
-            if (mask & 8) P.p8[(int64_t)I * bb + roff] = (uint8_t)encode_class(Sv, P8, lo16, tq[P8]);
+            if (mask & 8)
+                P.p8[(int64_t)I * bb + roff] = (uint8_t)encode_class(Sv, P8, lo16, mx ? xt[r][c >> 5] : tq[P8]);
             if (split) {  // FP32 copy as hi + mid + lo, each step exact in FP32
                 const float f = (float)Sv;
                 const uint16_t hi = f32_to_bf16(f);

@@ -15,6 +15,7 @@ struct Tiles {
     int32_t *tscale;      // nt*nt stored scale exponents
     int lo16;
     int lo32;             // FP32-class updates: 0 FP32 MFMA, 1 three-way BF16 split products
+    int lo8 = 0;          // FP8-class copies: 0 one scale per tile, 1 E8M0 scale per 32 K elements of a row
 };
 
 // Source of Sigma: the generator (sigma, x, rho, nugget), a kept FP64 copy
@@ -40,6 +41,7 @@ struct Panel {
     uint16_t *p32s;            // lo32 split: hi, mid, lo BF16 parts of the FP32 copy, each b*b row-major
     int8_t *poz = nullptr;     // lo64 INT8: per tile 15 residue planes of b*b bytes, row-major
     int32_t *pexp = nullptr;   // lo64 INT8: per tile b row exponents
+    uint8_t *p8x = nullptr;    // lo8 MX: per tile b rows x b/32 E8M0 bytes, row-major (block kb of row r at r*b/32 + kb)
 };
 
 // ---- tiles (k_tiles.hip)

@@ -62,6 +62,7 @@ struct mpchol_handle {
     uint16_t *p32s = nullptr;  // three BF16 parts of the FP32 copies (lo32 = BF16x3)
     uint16_t *p16 = nullptr;
     uint8_t *p8 = nullptr;
+    uint8_t *p8x = nullptr;      // lo8 MX: E8M0 block scales of the FP8 copies
     unsigned long long *pmax = nullptr;
     int32_t *pscale = nullptr;
     int8_t *poz = nullptr;       // lo64 INT8: residue planes of the FP64 copies, four sets
@@ -115,6 +116,7 @@ struct mpchol_handle {
         T.tscale = d_tscale;
         T.lo16 = o.lo16;
         T.lo32 = o.lo32;
+        T.lo8 = o.lo8;
         return T;
     }
     Source source() const
@@ -140,6 +142,7 @@ struct mpchol_handle {
         P.pscale = pscale + set * nt * 4;
         P.poz = poz ? poz + (size_t)set * nt * OZ_NMOD * bb : nullptr;
         P.pexp = pexp ? pexp + (size_t)set * nt * b : nullptr;
+        P.p8x = p8x ? p8x + (size_t)set * nt * bb / 32 : nullptr;
         return P;
     }
 };
@@ -211,7 +214,7 @@ static int dalloc(T **p, size_t bytes)
 
 static void release(mpchol_handle *h)
 {
-    void *ptrs[] = {h->slots, h->orig, h->d_sigma, h->d_x, h->p64, h->p32, h->p32s, h->p16, h->p8, h->pmax, h->pscale,
+    void *ptrs[] = {h->slots, h->orig, h->d_sigma, h->d_x, h->p64, h->p32, h->p32s, h->p16, h->p8, h->p8x, h->pmax, h->pscale,
                     h->poz, h->pexp, h->d_ozc,
                     h->d_map, h->d_tscale, h->d_fro2, h->d_amax, h->d_info, h->d_scalar, h->d_items, h->d_qmask,
                     h->d_all_items, h->d_partial, h->d_tres2, h->d_params, h->d_feats, h->d_est, h->d_zbuf};
@@ -242,6 +245,7 @@ void mpchol_default_opts(mpchol_opts *o)
     o->profile = 0;
     o->lo32 = MPCHOL_LO32_BF16X3;
     o->lo64 = MPCHOL_LO64_FP64;
+    o->lo8 = MPCHOL_LO8_TILE;
 }
 
 const char *mpchol_last_error(void) { return g_last_error; }
@@ -275,6 +279,7 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     if (opt.lo32 != MPCHOL_LO32_FP32 && opt.lo32 != MPCHOL_LO32_BF16X3) return MPCHOL_EINVAL;
     if (opt.lo64 != MPCHOL_LO64_FP64 && opt.lo64 != MPCHOL_LO64_INT8) return MPCHOL_EINVAL;
     if (opt.lo64 == MPCHOL_LO64_INT8 && tile > OZ_MAX_TILE) return MPCHOL_EUNSUPPORTED;
+    if (opt.lo8 != MPCHOL_LO8_TILE && opt.lo8 != MPCHOL_LO8_MX) return MPCHOL_EINVAL;
     if (opt.band < 0) return MPCHOL_EINVAL;
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
@@ -308,6 +313,7 @@ int mpchol_create(mpchol_t *hp, int64_t n, int32_t tile, const mpchol_opts *o)
     if (h->o.lo32 == MPCHOL_LO32_BF16X3) A(dalloc(&h->p32s, NSET * nt * bb * 3 * 2));
     A(dalloc(&h->p16, NSET * nt * bb * 2));
     A(dalloc(&h->p8, NSET * nt * bb));
+    if (h->o.lo8 == MPCHOL_LO8_MX) A(dalloc(&h->p8x, NSET * nt * bb / 32));
     if (h->o.lo64 == MPCHOL_LO64_INT8) {
         A(dalloc(&h->poz, NSET * nt * OZ_NMOD * bb));
         A(dalloc(&h->pexp, NSET * nt * (size_t)tile * 4));

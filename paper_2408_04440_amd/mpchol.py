@@ -23,6 +23,7 @@ RULE_FP64, RULE_NORM, RULE_BAND, RULE_USER, RULE_LEARNED = 0, 1, 2, 3, 4
 BAND_DP_SP, BAND_DP_SP_HP, BAND_DP_HP = 1, 2, 3
 LO32_FP32, LO32_BF16X3 = 0, 1
 LO64_FP64, LO64_INT8 = 0, 1
+LO8_TILE, LO8_MX = 0, 1
 MLP_NPARAM = 4996
 
 
@@ -36,7 +37,8 @@ class MpcholError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("lo16", C.c_int32), ("band", C.c_int32),
                 ("allowed", C.c_uint32), ("band_variant", C.c_int32), ("verify", C.c_int32),
-                ("verify_eps", C.c_double), ("profile", C.c_int32), ("lo32", C.c_int32), ("lo64", C.c_int32)]
+                ("verify_eps", C.c_double), ("profile", C.c_int32), ("lo32", C.c_int32), ("lo64", C.c_int32),
+                ("lo8", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -191,7 +193,7 @@ def mpchol_default_opts() -> Opts:
 
 
 def mpchol_create(n, tile, device=0, stream=None, lo16=LO16_F16, band=1, allowed=0xF, band_variant=BAND_DP_HP,
-                  verify=0, verify_eps=1e-9, profile=0, lo32=None, lo64=None):
+                  verify=0, verify_eps=1e-9, profile=0, lo32=None, lo64=None, lo8=None):
     o = mpchol_default_opts()
     o.device, o.stream, o.lo16, o.band = device, _stream_ptr(stream), lo16, band
     o.allowed, o.band_variant, o.verify, o.verify_eps, o.profile = allowed, band_variant, verify, verify_eps, profile
@@ -199,6 +201,8 @@ def mpchol_create(n, tile, device=0, stream=None, lo16=LO16_F16, band=1, allowed
         o.lo32 = lo32
     if lo64 is not None:
         o.lo64 = lo64
+    if lo8 is not None:
+        o.lo8 = lo8
     h = C.c_void_p()
     _chk(lib().mpchol_create(C.byref(h), int(n), int(tile), C.byref(o)), "mpchol_create")
     return h

@@ -111,15 +111,22 @@ def draws(n: int, ndraws: int, seed: int = SEED_DRAWS) -> np.ndarray:
     return np.asfortranarray(normal(seed, n * ndraws).astype(np.float32).reshape(ndraws, n).T)
 
 
-def int_lower(n: int, seed: int, lo: int = -3, hi: int = 3, diag_lo: int = 1, diag_hi: int = 4) -> np.ndarray:
+def int_lower(n: int, seed: int, lo: int = -3, hi: int = 3, diag_lo: int = 1, diag_hi: int = 4,
+              graded: bool = False) -> np.ndarray:
     """Random lower-triangular integer matrix with a positive diagonal.
 
     Small integer entries keep L0 @ L0.T exactly representable in FP64, so a
-    matrix built from it has a known exact Cholesky factor.
+    matrix built from it has a known exact Cholesky factor.  graded: entry
+    (i, j) below the diagonal is multiplied by 2^((i + j // 32) mod 4), so that
+    neighbouring rows and neighbouring 32-column blocks of a row differ in
+    magnitude (entries stay integers of at most two significant bits).
     """
     u = uniform01(seed, n * n).reshape(n, n)
     off = np.floor(lo + u * (hi - lo + 1)).astype(np.int64)
     off = np.clip(off, lo, hi)
+    if graded:
+        i, j = np.indices((n, n))
+        off = off << ((i + j // 32) % 4)
     d = np.floor(diag_lo + uniform01(seed + 7919, n) * (diag_hi - diag_lo + 1)).astype(np.int64)
     d = np.clip(d, diag_lo, diag_hi)
     L0 = np.tril(off, -1).astype(np.float64)

@@ -36,7 +36,9 @@ void orc_ozaki_gemm(int64_t m, int64_t n, int64_t k, const double *A, int64_t ld
                     double *D, int64_t ldd);
 float orc_split3(double v, int part);
 int64_t orc_mp_factor(int64_t n, int64_t b, const double *A, int64_t lda, const uint8_t *map, int lo16, double *Lhat,
-                      int64_t ldl, int32_t *tscale, int order, int lo32, int lo64, int band64);
+                      int64_t ldl, int32_t *tscale, int order, int lo32, int lo64, int band64, int lo8);
+int orc_mx_block_exp(double amax);
+void orc_mx_quantize(int64_t rows, int64_t cols, const double *X, int64_t ld, double *out, int64_t ldo, int32_t *texp);
 void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]);
 void orc_normal_draws(uint64_t seed, int64_t count, double *z, uint32_t *raw);
 int64_t orc_mlp_nparam(void);
@@ -102,6 +104,17 @@ int main(void)
         }
     }
     for (int c = 0; c < 256; ++c) (void)orc_e4m3_decode((uint8_t)c);
+    {  /* block-scaled copy with a ragged last block, and the exponent clamp */
+        double X[3 * 45], Q[3 * 45];
+        int32_t te[3 * 2];
+        for (int i = 0; i < 3 * 45; ++i) X[i] = (urand() - 0.5) * ldexp(1.0, (int)(urand() * 60) - 30);
+        orc_mx_quantize(3, 45, X, 3, Q, 3, te);
+        for (int i = 0; i < 3 * 45; ++i) {  /* relative bound, or half the subnormal spacing of the block */
+            const int t = te[i % 3 + (i / 3 / 32) * 3];
+            CHECK(fabs(Q[i] - X[i]) <= fmax(0.0626 * fabs(X[i]), ldexp(1.0, -10 - t)));
+        }
+        CHECK(orc_mx_block_exp(0.0) == 0 && orc_mx_block_exp(1e-300) == 127 && orc_mx_block_exp(1e300) == -127);
+    }
     for (int p = 0; p < 3; ++p) (void)orc_split3(urand() - 0.5, p);
 
     double *fro2 = malloc(nt * nt * sizeof(double)), *amax = malloc(nt * nt * sizeof(double));
@@ -117,8 +130,9 @@ int main(void)
         for (int order = 0; order <= 1; ++order)
             for (int lo32 = 0; lo32 <= 1; ++lo32)
                 for (int lo64 = 0; lo64 <= 1; ++lo64) {
+                    const int lo8 = (order + lo32 + lo64) & 1;
                     memset(Lh, 0, n * n * sizeof(double));
-                    CHECK(orc_mp_factor(n, b, A, n, map, lo16, Lh, n, ts, order, lo32, lo64, 1) == 0);
+                    CHECK(orc_mp_factor(n, b, A, n, map, lo16, Lh, n, ts, order, lo32, lo64, 1, lo8) == 0);
                     double an2 = 0.0;
                     CHECK(orc_residual_fro(n, A, n, Lh, n, &an2) <= 0.1 * an2);
                 }

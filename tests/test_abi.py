@@ -34,14 +34,14 @@ def test_struct_layouts_match_header(tmp_path):
 
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mpchol.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mpchol_opts), sizeof(mpchol_stats),'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mpchol_opts), sizeof(mpchol_stats),'
                     ' offsetof(mpchol_opts, verify_eps), offsetof(mpchol_stats, t_gemm_ms), offsetof(mpchol_stats, fallbacks),'
-                    ' offsetof(mpchol_stats, verify_first));return 0;}\n')
+                    ' offsetof(mpchol_stats, verify_first), offsetof(mpchol_opts, lo8));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(M.Opts), C.sizeof(M.Stats), M.Opts.verify_eps.offset, M.Stats.t_gemm_ms.offset,
-            M.Stats.fallbacks.offset, M.Stats.verify_first.offset]
+            M.Stats.fallbacks.offset, M.Stats.verify_first.offset, M.Opts.lo8.offset]
     assert got == want
 
 
@@ -63,6 +63,10 @@ def test_argument_validation_without_gpu():
     assert L.mpchol_create(C.byref(h), 0, 128, None) == -1
     assert L.mpchol_create(C.byref(h), 1024, 100, None) == -1   # tile not a multiple of 128
     assert L.mpchol_create(C.byref(h), 1024, 4096, None) == -1
+    for field, bad in (("lo8", 2), ("lo8", -1), ("lo64", 2), ("lo32", 7)):
+        o = M.mpchol_default_opts()
+        setattr(o, field, bad)
+        assert L.mpchol_create(C.byref(h), 1024, 128, C.byref(o)) == -1, field
     assert h.value is None
     assert L.mpchol_destroy(None) == 0
     assert L.mpchol_factor(None, None) == -1
@@ -89,7 +93,7 @@ def test_default_opts():
 
     o = M.mpchol_default_opts()
     assert o.band == 1 and o.allowed == 0xF and o.lo16 == M.LO16_F16 and o.verify_eps == 1e-9
-    assert o.lo32 == M.LO32_BF16X3
+    assert o.lo32 == M.LO32_BF16X3 and o.lo64 == M.LO64_FP64 and o.lo8 == M.LO8_TILE
 
 
 def test_sht_argument_checks_before_any_device_call():

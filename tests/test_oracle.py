@@ -518,6 +518,138 @@ def test_mp_factor_split_close_to_fp32(orc):
     assert 0 < d_so <= 4.0 * d_oo
 
 
+# ---------------------------------------------------------------- block-scaled FP8 copies
+def test_mx_block_exponent_brute_force(orc):
+    """The block exponent is the largest t in [-127, 127] (the E8M0 range) with
+    max 2^t <= 448, found here by trying every t; 0 for an all-zero block."""
+    u = synth.uniform01(91, 200)
+    vals = [448.0, 449.0, 447.9, 224.0, 1.0, 3.0, 0.75, 2.0 ** -120, 2.0 ** -140, 2.0 ** 119, 2.0 ** 140, 1e-300,
+            1e300, np.nextafter(448.0, 0.0), np.nextafter(448.0, 1e9)]
+    vals += list(np.ldexp(0.5 + u[:100], (u[100:] * 80 - 40).astype(int)))
+    for a in vals:
+        ok = [t for t in range(-127, 128) if a <= np.ldexp(448.0, -t)]
+        want = max(ok) if ok else -127
+        assert orc.mx_block_exp(a) == want, a
+    assert orc.mx_block_exp(0.0) == 0
+    # a maximum that is not finite has no exponent: 0, and the call returns
+    for fmt in (orc.E4M3, orc.F16):
+        assert orc.scale_exp(float("inf"), fmt) == 0 and orc.scale_exp(float("nan"), fmt) == 0
+    assert orc.mx_block_exp(float("inf")) == 0
+
+
+def test_mx_quantize_exact_for_short_significands(orc):
+    """Values of at most four significant bits are exact in E4M3 at any scale:
+    with a different exponent in every 32-element block of a row (spread over
+    2^-40 .. 2^40) the block-scaled copy reproduces them exactly, while one
+    scale per row block pair of 64 elements, or per whole array, does not (it
+    flushes the small blocks)."""
+    rows, cols = 6, 160
+    u = synth.uniform01(92, rows * cols).reshape(rows, cols)
+    k = np.floor(u * 31).astype(np.int64) - 15                       # -15 .. 15
+    d = np.floor(synth.uniform01(93, rows * cols).reshape(rows, cols) * 4).astype(int)   # 0 .. 3
+    e = np.floor(synth.uniform01(94, rows * cols // 32).reshape(rows, cols // 32) * 81).astype(int) - 40
+    X = np.ldexp(k.astype(float), d + np.repeat(e, 32, axis=1))
+    Q, texp = orc.mx_quantize(X)
+    assert np.array_equal(Q, X)
+    # the exponents follow the 32-element blocks along each row
+    for r in range(rows):
+        for c in range(cols // 32):
+            assert texp[r, c] == orc.mx_block_exp(np.max(np.abs(X[r, 32 * c:32 * c + 32])))
+    # a scale shared by 64 elements, or by the whole array, loses the small blocks
+    for width in (64, cols):
+        Y = np.zeros_like(X)
+        for c0 in range(0, cols, width):
+            for r in range(rows if width < cols else 1):
+                blk = X[r, c0:c0 + width] if width < cols else X
+                t = orc.mx_block_exp(np.max(np.abs(blk)))
+                q = np.array([np.ldexp(orc.round_to(float(np.float32(np.ldexp(v, t))), orc.E4M3), -t)
+                              for v in blk.ravel()]).reshape(blk.shape)
+                if width < cols:
+                    Y[r, c0:c0 + width] = q
+                else:
+                    Y = q
+        assert not np.array_equal(Y, X)
+
+
+def test_mx_quantize_equals_tile_copy_when_every_block_holds_the_max(orc):
+    """If every block of every row holds the array's largest |value|, every
+    block exponent is the per-tile exponent and the copy is the per-tile
+    E4M3 copy element for element."""
+    rows, cols = 5, 96
+    X = (synth.uniform01(95, rows * cols).reshape(rows, cols) - 0.5) * 7.0
+    M = 11.3
+    for r in range(rows):
+        for c in range(0, cols, 32):
+            X[r, c + (r * 7 + c) % 32] = M if (r + c) % 3 else -M
+    t = orc.scale_exp(M, orc.E4M3)
+    tile = np.array([np.ldexp(orc.round_to(float(np.float32(np.ldexp(v, t))), orc.E4M3), -t)
+                     for v in X.ravel()]).reshape(X.shape)
+    Q, texp = orc.mx_quantize(X)
+    assert np.all(texp == t)
+    assert np.array_equal(Q, tile)
+
+
+def test_mx_quantize_error_bound(orc):
+    """Every element is within the E4M3 rounding bound of its block: 2^-4 of
+    its magnitude in the normal range (plus the float step before it), or
+    half the subnormal spacing 2^-9 of the scaled block below it; a row's
+    last block may be shorter than 32."""
+    rows, cols = 7, 77
+    u = synth.uniform01(96, rows * cols).reshape(rows, cols)
+    X = (u - 0.5) * np.ldexp(1.0, (synth.uniform01(97, rows * cols).reshape(rows, cols) * 50 - 25).astype(int))
+    Q, texp = orc.mx_quantize(X)
+    assert texp.shape == (rows, 3)
+    for r in range(rows):
+        for c in range(cols):
+            t = texp[r, c // 32]
+            bound = max(2.0 ** -4 * (1 + 2.0 ** -19) * abs(X[r, c]), np.ldexp(1.0, -10 - t))
+            assert abs(Q[r, c] - X[r, c]) <= bound
+
+
+@pytest.mark.parametrize("kind", ["all8", "mixed"])
+def test_mp_factor_mx_integer_exact(orc, kind):
+    """A = L0 L0^T with graded integers (magnitudes that change from row to row
+    and from one 32-column block to the next): with block-scaled FP8 copies
+    the replay returns L0 exactly, in an all-FP8 map and in a map over every
+    class -- a copy read at the wrong block's scale would not."""
+    n, b = 320, 64
+    L0 = synth.int_lower(n, 29, graded=True)
+    A = L0 @ L0.T
+    nt = n // b
+    if kind == "all8":
+        cmap = np.tril(np.full((nt, nt), 3, np.uint8), -1)
+    else:
+        u = synth.uniform01(31, nt * nt).reshape(nt, nt)
+        cmap = np.tril(np.floor(u * 4).astype(np.uint8), -1)
+    Lh, info, _ = orc.mp_factor(A, b, cmap, lo8=1)
+    assert info == 0 and np.array_equal(Lh, L0)
+
+
+def test_mp_factor_mx_invariants(orc):
+    """Where block scaling cannot change the replay, it does not: in an all-FP8
+    map every panel tile is stored on its tile's E4M3 grid, which every finer
+    block scale represents exactly, so the block-scaled copies equal the
+    per-tile ones and the factors agree bit for bit; likewise on a map
+    without FP8 tiles.  (The copies of panel tiles stored in a higher class do
+    differ: the graded integer test above reads them at their block scales.)"""
+    sigma, x = synth.workload(20)
+    A = orc.cov_dense(sigma, x, 5.0, 1e-1)
+    b, nt = 64, 7
+    n = b * nt - 20
+    A = A[:n, :n]
+    cmap = np.tril(np.full((nt, nt), 3, np.uint8), -1)
+    Lt, it, tt = orc.mp_factor(A, b, cmap)
+    Lm, im, tm = orc.mp_factor(A, b, cmap, lo8=1)
+    assert it == 0 and im == 0 and np.array_equal(tt, tm)
+    assert np.array_equal(Lm, Lt)
+    L, _ = orc.potrf(A)
+    assert 0 < np.linalg.norm(Lt - L) / np.linalg.norm(L) <= 2.0 ** -4
+    cmap2 = np.tril(np.full((nt, nt), 2, np.uint8), -1)
+    La, _, _ = orc.mp_factor(A, b, cmap2)
+    Lb, _, _ = orc.mp_factor(A, b, cmap2, lo8=1)
+    assert np.array_equal(La, Lb)
+
+
 # ---------------------------------------------------------------- Adam against hand-derived steps
 def test_adam_two_steps_golden(orc):
     """Two Adam steps (Kingma & Ba, with bias correction) against values derived
