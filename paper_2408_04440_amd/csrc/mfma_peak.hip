@@ -112,6 +112,19 @@ struct FP8_16x16x128 {
         return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
     }
 };
+// The same instruction with E8M0 scale operands (byte 127 = 2^0 per lane,
+// not a constant zero, which the compiler turns into the unscaled form).
+struct FP8_16x16x128_MX {
+    typedef i32x8 op_t;
+    typedef f32x4 acc_t;
+    static constexpr double FLOPS = 2.0 * 16 * 16 * 128;
+    __device__ static op_t op(int t) { return FP8_16x16x128::op(t); }
+    __device__ static acc_t mma(op_t a, op_t b, acc_t c)
+    {
+        const int s = 127 + (int)(threadIdx.x >> 10);
+        return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, s, 0, s);
+    }
+};
 struct FP8_32x32x64 {
     typedef i32x8 op_t;
     typedef f32x16 acc_t;
@@ -201,6 +214,7 @@ int main(int argc, char **argv)
     run<BF16_16x16x32>("bf16 16x16x32", 2500.0, cus, out, blocks, target_ms);
     run<FP8_16x16x32>("fp8 16x16x32 (fp8_fp8)", 5000.0, cus, out, blocks, target_ms);
     run<FP8_16x16x128>("fp8 16x16x128 (f8f6f4)", 5000.0, cus, out, blocks, target_ms);
+    run<FP8_16x16x128_MX>("fp8 16x16x128 (f8f6f4, E8M0 scales)", 5000.0, cus, out, blocks, target_ms);
     run<FP8_32x32x64>("fp8 32x32x64 (f8f6f4)", 5000.0, cus, out, blocks, target_ms);
     CK(hipFree(out));
     return 0;
