@@ -384,19 +384,12 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
             constexpr int KS = RM<KIND>::KSTEP;  // K per instruction; KS / 4 per lane
             const int kb = (s * KS + (KS / 4) * gg) * (int)sizeof(T);
             F fa[S::MB], fb[S::NB];
-            int sa[S::MB], sb[S::NB];
             if constexpr (MX) {
                 // the block-scaled instruction splits K into two halves of 64:
                 // lane group gg passes K elements 16 gg .. 16 gg + 15 of each
                 // half, and block b (K 32 b .. 32 b + 31) takes lane group b's
                 // scale; so each lane reads those two 16-byte pieces of its row
-                // and passes the scale of block gg.  The scale words are read
-                // first: LDS reads complete in order, and every product needs them.
-                const uint32_t *ss = Ss + cur * (BM + BN);
-#pragma unroll
-                for (int m = 0; m < S::MB; ++m) sa[m] = (ss[wm * (BM / WM) + m * 16 + gi] >> (8 * gg)) & 0xff;
-#pragma unroll
-                for (int n = 0; n < S::NB; ++n) sb[n] = (ss[BM + wn * (BN / WN) + n * 16 + gi] >> (8 * gg)) & 0xff;
+                // and passes the scale of block gg
 #pragma unroll
                 for (int m = 0; m < S::MB; ++m) fa[m] = mx_frag(as + m * 16 * S::LDB + 16 * gg);
 #pragma unroll
@@ -408,6 +401,12 @@ __device__ inline void rm_block(const typename RM<KIND>::T *__restrict__ A, int6
                 for (int n = 0; n < S::NB; ++n) fb[n] = *(const F *)(bs + n * 16 * S::LDB + kb);
             }
             if constexpr (MX) {
+                const uint32_t *ss = Ss + cur * (BM + BN);
+                int sa[S::MB], sb[S::NB];
+#pragma unroll
+                for (int m = 0; m < S::MB; ++m) sa[m] = (ss[wm * (BM / WM) + m * 16 + gi] >> (8 * gg)) & 0xff;
+#pragma unroll
+                for (int n = 0; n < S::NB; ++n) sb[n] = (ss[BM + wn * (BN / WN) + n * 16 + gi] >> (8 * gg)) & 0xff;
 #pragma unroll
                 for (int m = 0; m < S::MB; ++m)
 #pragma unroll
