@@ -37,7 +37,7 @@ extern "C" {
 
 /* status codes */
 #define MPCHOL_OK 0
-#define MPCHOL_NOT_SPD 1       /* a diagonal pivot was not positive (or NaN) */
+#define MPCHOL_NOT_SPD 1       /* a diagonal pivot was not positive (or NaN), or the factor took an Inf or NaN */
 #define MPCHOL_EINVAL (-1)     /* invalid argument */
 #define MPCHOL_ENOMEM (-2)     /* device allocation failed */
 #define MPCHOL_EHIP (-3)       /* a HIP runtime call failed */
@@ -193,8 +193,10 @@ int mpchol_set_samples(mpchol_t h, const double *xi, int64_t ldxi, int64_t m, do
 int mpchol_precision_map(mpchol_t h, int32_t rule, double eps, const uint8_t *user_map, uint8_t *map_out);
 
 /* Factor the loaded matrix in place (right-looking tile algorithm, Sec. V.A).
- * *info = 0 on success, else the 1-based global column of the first failing
- * pivot (returns MPCHOL_NOT_SPD).  Under RULE_LEARNED with opts.verify set,
+ * *info = 0 on success, else the smallest 1-based global column of a failing
+ * pivot or of an Inf or NaN in an off-diagonal factor tile, as the panel
+ * solve writes it -- also where the tile is stored in a format that would
+ * saturate it (returns MPCHOL_NOT_SPD).  Under RULE_LEARNED with opts.verify set,
  * a backward error above opts.verify_eps (or a failing pivot) triggers a
  * refactorization under RULE_NORM and then RULE_FP64 (counted in stats);
  * MPCHOL_EBUDGET if all fail.  Synchronizes once at the end. */

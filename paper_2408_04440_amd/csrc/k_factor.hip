@@ -75,7 +75,10 @@ __global__ __launch_bounds__(64) void potrf_block_kernel(double *tile, int b, in
 // mode 0: the panel of step k -- item I = k+1+blockIdx.y, W = tile (I,k) in
 //         its work precision (FP64, or FP32 for lower classes), X = p64[I];
 //         the strip's largest |X| is folded into pmax[I] (atomic max of the
-//         FP64 bits, which order like the values; the caller zeroes pmax);
+//         FP64 bits, which order like the values; the caller zeroes pmax),
+//         and the first column holding an Inf or NaN into P.info (every
+//         off-diagonal factor tile passes here, so a non-finite value is
+//         reported even where a low-precision code would saturate it);
 // mode 1: one FP64 strip set in place (W = X = xin, leading dimension ldin).
 // nL is a multiple of 32.
 __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, const double *__restrict__ L, int64_t ldl,
@@ -105,7 +108,8 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int gi = lane & 15, gg = lane >> 4;
     double *Xs = X + row0;
-    double xmax = 0.0;  // wave 0: largest |X| written
+    double xmax = 0.0;     // wave 0: largest |X| written
+    int bad = 0x7FFFFFFF;  // wave 0: first column (in the tile) of a non-finite X written
 
     for (int cb = 0; cb < nL; cb += 32) {
         // this column block's right-hand side and diagonal block, read before
@@ -197,6 +201,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
             for (int c = 0; c < 32; ++c) {
                 Xs[lane + (int64_t)(cb + c) * ldx] = t[c];
                 xmax = fmax(xmax, fabs(t[c]));
+                if (!(fabs(t[c]) <= 1.7976931348623157e308)) bad = min(bad, cb + c);
             }
         }
         __syncthreads();  // the solved columns are read back by the next column block
@@ -205,6 +210,10 @@ __global__ __launch_bounds__(256) void trsm_kernel(Tiles T, Panel P, int k, cons
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) xmax = fmax(xmax, __shfl_xor(xmax, off));
         if (lane == 0) atomicMax(P.pmax + k + 1 + blockIdx.y, (unsigned long long)__double_as_longlong(xmax));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) bad = min(bad, __shfl_xor(bad, off));
+        if (lane == 0 && bad != 0x7FFFFFFF && P.info)
+            atomicMin(P.info, (unsigned long long)((int64_t)k * T.b + bad + 1));
     }
 }
 

@@ -42,6 +42,8 @@ struct Panel {
     int8_t *poz = nullptr;     // lo64 INT8: per tile 15 residue planes of b*b bytes, row-major
     int32_t *pexp = nullptr;   // lo64 INT8: per tile b row exponents
     uint8_t *p8x = nullptr;    // lo8 MX: per tile b rows x b/32 E8M0 bytes, row-major (block kb of row r at r*b/32 + kb)
+    unsigned long long *info = nullptr;  // breakdown column (1-based, atomic minimum): the panel TRSM
+                                         // reports the first column where it writes an Inf or NaN
 };
 
 // ---- tiles (k_tiles.hip)

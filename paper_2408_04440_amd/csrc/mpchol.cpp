@@ -143,6 +143,7 @@ struct mpchol_handle {
         P.poz = poz ? poz + (size_t)set * nt * OZ_NMOD * bb : nullptr;
         P.pexp = pexp ? pexp + (size_t)set * nt * b : nullptr;
         P.p8x = p8x ? p8x + (size_t)set * nt * bb / 32 : nullptr;
+        P.info = d_info;
         return P;
     }
 };

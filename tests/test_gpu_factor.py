@@ -144,6 +144,29 @@ def test_nan_entry_reports_info():
         mod.mpchol_destroy(h)
 
 
+@pytest.mark.parametrize("cls", [3, 0])
+def test_inf_entry_reports_its_column(cls):
+    """An Inf below the diagonal (row 300, column 10) in a map of FP8 tiles, or
+    of FP64 tiles: the panel solve writes the Inf into column 10 of the factor
+    and the call returns MPCHOL_NOT_SPD with info 11 -- also where the E4M3
+    code would saturate it to 448."""
+    n, tile = 512, 128
+    L0 = synth.int_lower(n, 5)
+    A = L0 @ L0.T
+    A[300, 10] = A[10, 300] = np.inf
+    nt = n // tile
+    um = np.asfortranarray(np.tril(np.full((nt, nt), cls, np.uint8), -1))
+    log(f"inf entry, class {cls}")
+    mod = M()
+    h = mod.mpchol_create(n, tile, band=0)
+    try:
+        mod.mpchol_set_matrix(h, A)
+        mod.mpchol_precision_map(h, mod.RULE_USER, 1e-9, um)
+        assert mod.mpchol_factor(h) == 11
+    finally:
+        mod.mpchol_destroy(h)
+
+
 def test_call_order_and_arguments():
     import ctypes as C
 
